@@ -1,0 +1,76 @@
+"""Gate-SDF evaluation (oracle side), float64.
+
+* Analytic guidance field, Section III-A eqs. 1-2:
+  r(p) = max(|y|, |z|) on the gate plane x = 0, and
+  s_guide(p) = c + |x| tan(alpha) - r(p).  The paper leaves c and alpha
+  open; with the 1.0 m inner opening of Section V, c = 0.5 m, and
+  tan(alpha) = 0.5 is this build's choice.
+* Learned decoder g_phi(z, PE(p)), Section III-B: an MLP on the
+  concatenation of the encoded query point and the latent code z.  Reading:
+  PE is the identity (input width 3 + 64 = 67), the coordinates occupy input
+  columns 0..2 and the latent columns 3..66, hidden layers use softplus
+  (beta = 1) and the output layer is linear so the field can be negative.
+  The paper's Fig. 2 duplicates z for every query and concatenates;
+  ``mlp_concat`` does exactly that, ``mlp_fold`` applies the first layer's
+  latent block once per gate (an exact re-association).
+* Several gates per solve (this build's multi-gate workloads): the field at
+  a point is the maximum over gates of each gate's field (union of the safe
+  funnels); with one gate this is the paper's single-latent case.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .precision import bf16_round, e4m3_round
+
+C_HALF_WIDTH = 0.5
+TAN_ALPHA = 0.5
+
+
+def softplus(x):
+    """log(1 + exp(x)) in the overflow-free form max(x, 0) + log1p(exp(-|x|))."""
+    return np.maximum(x, 0.0) + np.log1p(np.exp(-np.abs(x)))
+
+
+def gate_sdf_analytic(pg, c=C_HALF_WIDTH, tan_alpha=TAN_ALPHA):
+    """s_guide at gate-frame points pg (..., 3): eqs. 1-2."""
+    r = np.maximum(np.abs(pg[..., 1]), np.abs(pg[..., 2]))
+    return c + np.abs(pg[..., 0]) * tan_alpha - r
+
+
+def _hidden_input(h, layer, contract, act_scales):
+    """Operand of hidden layer ``layer`` (1-based H x H layer) under a contract."""
+    if contract == "bf16":
+        return bf16_round(h)
+    if contract == "fp8":
+        s = act_scales[layer - 1]
+        return e4m3_round(h / s) * s
+    return h
+
+
+def _mlp_tail(h, W, b, contract, act_scales):
+    """Layers 2..L+1 of the decoder from the first hidden activation h."""
+    n = len(W)
+    for l in range(1, n - 1):
+        a = _hidden_input(h, l, contract, act_scales)
+        h = softplus(a @ W[l].T + b[l])
+    return h @ W[n - 1].T + b[n - 1]
+
+
+def mlp_concat(pg, z, W, b, contract="fp32", act_scales=None):
+    """Decoder on the literal concatenation [p; z] for points pg (N, 3).
+
+    ``W``/``b`` are float64 arrays of the (possibly quantised) layers,
+    W[l] of shape (n_out, n_in); returns s of shape (N,).
+    """
+    x = np.concatenate([pg, np.broadcast_to(z, (pg.shape[0], z.shape[-1]))], axis=1)
+    h = softplus(x @ W[0].T + b[0])
+    return _mlp_tail(h, W, b, contract, act_scales)[:, 0]
+
+
+def mlp_fold(pg, z, W, b, contract="fp32", act_scales=None):
+    """Same decoder with the latent block of layer 1 applied once:
+    c = W1[:, 3:] z + b1, h1 = softplus(W1[:, :3] p + c)."""
+    c = W[0][:, 3:] @ z + b[0]
+    h = softplus(pg @ W[0][:, :3].T + c)
+    return _mlp_tail(h, W, b, contract, act_scales)[:, 0]
