@@ -20,6 +20,7 @@
 from __future__ import annotations
 
 import numpy as np
+import torch
 
 from .precision import bf16_round, e4m3_round
 
@@ -27,9 +28,14 @@ C_HALF_WIDTH = 0.5
 TAN_ALPHA = 0.5
 
 
+def _softplus_t(x):
+    """softplus on a float64 torch tensor (CPU, multithreaded elementwise ops)."""
+    return torch.clamp_min(x, 0.0) + torch.log1p(torch.exp(-torch.abs(x)))
+
+
 def softplus(x):
     """log(1 + exp(x)) in the overflow-free form max(x, 0) + log1p(exp(-|x|))."""
-    return np.maximum(x, 0.0) + np.log1p(np.exp(-np.abs(x)))
+    return _softplus_t(torch.as_tensor(np.asarray(x, dtype=np.float64))).numpy()
 
 
 def gate_sdf_analytic(pg, c=C_HALF_WIDTH, tan_alpha=TAN_ALPHA):
@@ -38,13 +44,17 @@ def gate_sdf_analytic(pg, c=C_HALF_WIDTH, tan_alpha=TAN_ALPHA):
     return c + np.abs(pg[..., 0]) * tan_alpha - r
 
 
+def _t(a):
+    return torch.as_tensor(np.asarray(a, dtype=np.float64))
+
+
 def _hidden_input(h, layer, contract, act_scales):
     """Operand of hidden layer ``layer`` (1-based H x H layer) under a contract."""
     if contract == "bf16":
-        return bf16_round(h)
+        return _t(bf16_round(h.numpy()))
     if contract == "fp8":
         s = act_scales[layer - 1]
-        return e4m3_round(h / s) * s
+        return _t(e4m3_round(h.numpy() / s) * s)
     return h
 
 
@@ -53,8 +63,8 @@ def _mlp_tail(h, W, b, contract, act_scales):
     n = len(W)
     for l in range(1, n - 1):
         a = _hidden_input(h, l, contract, act_scales)
-        h = softplus(a @ W[l].T + b[l])
-    return h @ W[n - 1].T + b[n - 1]
+        h = _softplus_t(a @ _t(W[l]).T + _t(b[l]))
+    return h @ _t(W[n - 1]).T + _t(b[n - 1])
 
 
 def mlp_concat(pg, z, W, b, contract="fp32", act_scales=None):
@@ -64,13 +74,13 @@ def mlp_concat(pg, z, W, b, contract="fp32", act_scales=None):
     W[l] of shape (n_out, n_in); returns s of shape (N,).
     """
     x = np.concatenate([pg, np.broadcast_to(z, (pg.shape[0], z.shape[-1]))], axis=1)
-    h = softplus(x @ W[0].T + b[0])
-    return _mlp_tail(h, W, b, contract, act_scales)[:, 0]
+    h = _softplus_t(_t(x) @ _t(W[0]).T + _t(b[0]))
+    return _mlp_tail(h, W, b, contract, act_scales)[:, 0].numpy()
 
 
 def mlp_fold(pg, z, W, b, contract="fp32", act_scales=None):
     """Same decoder with the latent block of layer 1 applied once:
     c = W1[:, 3:] z + b1, h1 = softplus(W1[:, :3] p + c)."""
-    c = W[0][:, 3:] @ z + b[0]
-    h = softplus(pg @ W[0][:, :3].T + c)
-    return _mlp_tail(h, W, b, contract, act_scales)[:, 0]
+    c = _t(W[0])[:, 3:] @ _t(z) + _t(b[0])
+    h = _softplus_t(_t(pg) @ _t(W[0])[:, :3].T + c)
+    return _mlp_tail(h, W, b, contract, act_scales)[:, 0].numpy()

@@ -1,0 +1,132 @@
+// Device-side building blocks of one MPPI iteration (gfx950).
+//
+// Noise: Philox4x64-10 (Salmon et al., SC'11) keyed by (seed, 0) with
+// counter (k, t, instance, tick); each 64-bit word yields one uniform from
+// its top 23 bits, Box-Muller (1958) turns two uniforms into two normals.
+// Dynamics: collective thrust + body rates, attitude held over the step for
+// the acceleration, exact exponential map for the attitude (Section IV-A uses
+// a standard quadrotor model; the input form is this library's reading).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "solve_desc.hpp"
+
+namespace mppi {
+
+// ---------------------------------------------------------------- Philox4x64-10
+struct u64x4 { uint64_t x0, x1, x2, x3; };
+
+__device__ __forceinline__ u64x4 philox4x64_10(u64x4 c, uint64_t k0, uint64_t k1) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t hi0 = __umul64hi(M0, c.x0), lo0 = M0 * c.x0;
+    const uint64_t hi1 = __umul64hi(M1, c.x2), lo1 = M1 * c.x2;
+    c = u64x4{hi1 ^ c.x1 ^ k0, lo1, hi0 ^ c.x3 ^ k1, lo0};
+    k0 += W0;
+    k1 += W1;
+  }
+  return c;
+}
+
+// Top 23 bits -> (m + 1/2) 2^-23, exact in float32, strictly inside (0, 1).
+__device__ __forceinline__ float uniform23(uint64_t w) {
+  return ((float)(uint32_t)(w >> 41) + 0.5f) * 0x1.0p-23f;
+}
+
+// Four standard normals for (rollout k, step t) of a solve.
+__device__ __forceinline__ void normals4(uint64_t seed, uint64_t inst, uint64_t tick, uint32_t k,
+                                         uint32_t t, float n[4]) {
+  const u64x4 w = philox4x64_10(u64x4{k, t, inst, tick}, seed, 0ull);
+  const float u0 = uniform23(w.x0), u1 = uniform23(w.x1);
+  const float u2 = uniform23(w.x2), u3 = uniform23(w.x3);
+  const float r01 = sqrtf(-2.0f * logf(u0));
+  const float r23 = sqrtf(-2.0f * logf(u2));
+  float s, c;
+  sincospif(2.0f * u1, &s, &c);
+  n[0] = r01 * c;
+  n[1] = r01 * s;
+  sincospif(2.0f * u3, &s, &c);
+  n[2] = r23 * c;
+  n[3] = r23 * s;
+}
+
+// u = clip(U_nom[t] + L n, lo, hi) with L lower triangular (row-major 4x4).
+__device__ __forceinline__ void sample_control(const SolveDesc& d, uint32_t k, uint32_t t,
+                                               uint64_t tick, float u[4]) {
+  float n[4];
+  normals4(d.seed, d.instance_id, tick, k, t, n);
+  const int ti = t < (uint32_t)d.U_len ? (int)t : d.U_len - 1;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    float e = 0.0f;
+#pragma unroll
+    for (int j = 0; j <= c; ++j) e = fmaf(d.L[c * 4 + j], n[j], e);
+    const float nom = d.U_src ? (float)d.U_src[ti * 4 + c] : (float)d.hover[c];
+    u[c] = fminf(fmaxf(nom + e, d.u_lo[c]), d.u_hi[c]);
+  }
+}
+
+// ---------------------------------------------------------------- dynamics
+// Rollout state in the local frame: dp is the position minus p0 + v0 t dt
+// (deviation from the initial ballistic drift), dv = v - v0, q attitude.
+struct RolloutState {
+  float dp[3], dv[3], q[4];
+};
+
+__device__ __forceinline__ void quad_step(RolloutState& s, const float u[4], float dt, float inv_m,
+                                          float g) {
+  const float w = s.q[0], x = s.q[1], y = s.q[2], z = s.q[3];
+  // R(q) e3: body z axis in the world frame.
+  const float bx = 2.0f * (x * z + w * y);
+  const float by = 2.0f * (y * z - w * x);
+  const float bz = 1.0f - 2.0f * (x * x + y * y);
+  const float f = u[0] * inv_m;
+  const float a[3] = {f * bx, f * by, fmaf(f, bz, -g)};
+  const float hdt2 = 0.5f * dt * dt;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    s.dp[i] = fmaf(a[i], hdt2, fmaf(s.dv[i], dt, s.dp[i]));
+    s.dv[i] = fmaf(a[i], dt, s.dv[i]);
+  }
+  // q <- q (x) [cos(|w| dt/2), sin(|w| dt/2) w/|w|]
+  const float wx = u[1], wy = u[2], wz = u[3];
+  const float nrm = sqrtf(wx * wx + wy * wy + wz * wz);
+  const float half = 0.5f * nrm * dt;
+  float sh, ch;
+  sincosf(half, &sh, &ch);
+  const float so = half < 1e-4f ? 0.5f * dt * (1.0f - half * half * (1.0f / 6.0f)) : sh / nrm;
+  const float rw = ch, rx = so * wx, ry = so * wy, rz = so * wz;
+  s.q[0] = w * rw - x * rx - y * ry - z * rz;
+  s.q[1] = w * rx + x * rw + y * rz - z * ry;
+  s.q[2] = w * ry - x * rz + y * rw + z * rx;
+  s.q[3] = w * rz + x * ry - y * rx + z * rw;
+}
+
+// 1 - cos(psi - psi_los) for the yaw psi of q and the bearing of (lx, ly)
+// (eq. 6); atan2(0, 0) = 0 conventions for degenerate vectors.
+__device__ __forceinline__ float alignment_term(const float q[4], float lx, float ly) {
+  const float w = q[0], x = q[1], y = q[2], z = q[3];
+  float hx = 1.0f - 2.0f * (y * y + z * z), hy = 2.0f * (w * z + x * y);
+  float hn = sqrtf(hx * hx + hy * hy);
+  if (hn == 0.0f) { hx = 1.0f; hy = 0.0f; hn = 1.0f; }
+  float ln = sqrtf(lx * lx + ly * ly);
+  if (ln == 0.0f) { lx = 1.0f; ly = 0.0f; ln = 1.0f; }
+  return 1.0f - (hx * lx + hy * ly) / (hn * ln);
+}
+
+// ---------------------------------------------------------------- activations
+// softplus(x) = log(1 + e^x) = max(x, 0) + log1p(e^-|x|): accurate form.
+__device__ __forceinline__ float softplus_accurate(float x) {
+  return fmaxf(x, 0.0f) + log1pf(expf(-fabsf(x)));
+}
+
+// Analytic guidance field of eqs. 1-2 in gate-frame coordinates.
+__device__ __forceinline__ float gate_sdf_analytic(float px, float py, float pz, float c,
+                                                   float tan_a) {
+  return c + fabsf(px) * tan_a - fmaxf(fabsf(py), fabsf(pz));
+}
+
+}  // namespace mppi

@@ -1,0 +1,168 @@
+// Host-only building blocks of the engine, free of HIP calls so that they can
+// be exercised without a GPU: the device-memory arena (first-fit with
+// coalescing), the footprint of a solve and the FIFO admission queue of the
+// served path.
+#pragma once
+#include <stdint.h>
+
+#include <deque>
+#include <map>
+#include <vector>
+
+namespace mppi {
+
+constexpr uint64_t kAlign = 256;
+
+inline uint64_t align_up(uint64_t x, uint64_t a = kAlign) { return (x + a - 1) / a * a; }
+
+// First-fit allocator over offsets [0, capacity) with neighbour coalescing.
+class Arena {
+ public:
+  explicit Arena(uint64_t capacity = 0) { reset(capacity); }
+  void reset(uint64_t capacity) {
+    cap_ = capacity;
+    in_use_ = 0;
+    peak_ = 0;
+    free_.clear();
+    if (capacity) free_[0] = capacity;
+  }
+  bool alloc(uint64_t bytes, uint64_t* offset) {
+    bytes = align_up(bytes ? bytes : 1);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= bytes) {
+        const uint64_t off = it->first, rest = it->second - bytes;
+        free_.erase(it);
+        if (rest) free_[off + bytes] = rest;
+        in_use_ += bytes;
+        if (in_use_ > peak_) peak_ = in_use_;
+        *offset = off;
+        return true;
+      }
+    }
+    return false;
+  }
+  void release(uint64_t offset, uint64_t bytes) {
+    bytes = align_up(bytes ? bytes : 1);
+    in_use_ -= bytes;
+    auto it = free_.emplace(offset, bytes).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  uint64_t capacity() const { return cap_; }
+  uint64_t in_use() const { return in_use_; }
+  uint64_t peak() const { return peak_; }
+  uint64_t largest_free() const {
+    uint64_t m = 0;
+    for (auto& kv : free_) m = kv.second > m ? kv.second : m;
+    return m;
+  }
+  size_t fragments() const { return free_.size(); }
+
+ private:
+  uint64_t cap_ = 0, in_use_ = 0, peak_ = 0;
+  std::map<uint64_t, uint64_t> free_;
+};
+
+// Byte layout of one solve's device block (descriptor, request data, buffers).
+struct SolveLayout {
+  uint64_t desc, U, Rt, base, cfold, los;            // request part (uploaded)
+  uint64_t samples, pos, sdf, Jpart, J, wt, wn, result, partials, tiles_done;
+  uint64_t upload_bytes, total;
+};
+
+inline SolveLayout solve_layout(int K, int T, int G, int H, bool fused, int n_tiles) {
+  SolveLayout L{};
+  uint64_t o = 0;
+  auto take = [&](uint64_t bytes) { const uint64_t r = o; o = align_up(o + bytes); return r; };
+  L.desc = take(512);
+  L.U = take(8ull * 4 * T);
+  L.Rt = take(4ull * 9 * G);
+  L.base = take(4ull * 3 * G * (T + 1));
+  L.cfold = take(4ull * G * H);
+  L.los = take(4ull * 2 * T);
+  L.upload_bytes = o;
+  L.result = take(8ull * (4 * T + 10));
+  L.J = take(4ull * K);
+  L.wn = take(8ull * K);
+  if (!fused) {
+    L.samples = take(4ull * 4 * T * K);
+    L.pos = take(4ull * 3 * (T + 1) * K);
+    L.sdf = take(4ull * T * K);
+    L.Jpart = take(4ull * K);
+    L.wt = take(8ull * K);
+  } else {
+    L.partials = take(8ull * (2 + 4 * T) * n_tiles);
+    L.tiles_done = take(64);
+  }
+  L.total = o;
+  return L;
+}
+
+// FIFO queue with budget admission: the head is admitted when its footprint
+// fits the free budget and an in-flight slot is free; requests never overtake
+// the head (no starvation of large requests), except that a head blocked only
+// by its instance being busy lets later requests of other instances pass.
+struct AdmissionItem {
+  uint64_t ticket;
+  uint64_t instance_id;
+  uint64_t footprint;
+};
+
+class Admission {
+ public:
+  Admission(uint64_t budget, int max_inflight, int queue_depth)
+      : budget_(budget), max_inflight_(max_inflight), depth_(queue_depth) {}
+  // 0 = queued, -3 = queue full, -2 = can never fit
+  int push(const AdmissionItem& it) {
+    if (it.footprint > budget_) return -2;
+    if ((int)q_.size() >= depth_) return -3;
+    q_.push_back(it);
+    return 0;
+  }
+  // Pops every item admissible now, in FIFO order, given the busy instances.
+  template <class BusyFn>
+  std::vector<AdmissionItem> admit(BusyFn instance_busy) {
+    std::vector<AdmissionItem> out;
+    auto taken = [&](uint64_t id) {
+      for (auto& o : out) if (o.instance_id == id) return true;
+      return false;
+    };
+    for (auto it = q_.begin(); it != q_.end();) {
+      if (inflight_ >= max_inflight_) break;
+      if (instance_busy(it->instance_id) || taken(it->instance_id)) { ++it; continue; }
+      if (in_use_ + it->footprint > budget_) break;
+      in_use_ += it->footprint;
+      ++inflight_;
+      out.push_back(*it);
+      it = q_.erase(it);
+    }
+    return out;
+  }
+  void complete(uint64_t footprint) {
+    in_use_ -= footprint;
+    --inflight_;
+  }
+  size_t queued() const { return q_.size(); }
+  int inflight() const { return inflight_; }
+  uint64_t in_use() const { return in_use_; }
+  uint64_t budget() const { return budget_; }
+
+ private:
+  uint64_t budget_;
+  int max_inflight_, depth_;
+  int inflight_ = 0;
+  uint64_t in_use_ = 0;
+  std::deque<AdmissionItem> q_;
+};
+
+}  // namespace mppi

@@ -1,0 +1,47 @@
+// Host-side launchers of the device kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "../../include/mppi.h"
+
+#include "solve_desc.hpp"
+#include "weights.hpp"
+
+namespace mppi {
+
+struct PlainShape {
+  int K, T, G, sdf_kind;
+};
+
+// Plain path: rollout -> SDF -> cost -> LSE -> weighted average for one solve
+// whose descriptor is at device address dd.  The optional events bracket the
+// SDF kernel (the dominant one).
+hipError_t launch_plain(const SolveDesc* dd, const PlainShape& shape, const DeviceWeights& w,
+                        hipStream_t s, hipEvent_t sdf_begin, hipEvent_t sdf_end);
+
+// Fused path: one persistent launch over the tiles of a batch of solves.
+struct FusedBatch {
+  const SolveDesc* descs;    // device array of n_solves descriptors
+  const int2* tiles;         // device array of (solve index, first rollout)
+  int n_tiles;
+  uint32_t* tile_counter;    // device work counter (zeroed by the launcher)
+};
+
+hipError_t launch_fused(const FusedBatch& b, const DeviceWeights& w, int max_T, hipStream_t s,
+                        hipEvent_t begin, hipEvent_t end);
+
+// Rollouts per fused tile for a precision / width (the unit of work of the
+// persistent kernel).
+int fused_tile_rollouts(int precision, int H, int G);
+
+// Quantise and pack the hidden H x H layers for a low-precision variant
+// (BF16, BF16X2, FP8) in the fused kernel's operand order.  Returns an
+// mppi_status.
+int pack_lowp_weights(int precision, int H, int n_hidden, const mppi_sdf_weights* w,
+                      std::vector<uint8_t>& blob, std::vector<float>& w_scale,
+                      std::vector<float>& a_scale, std::vector<float>& a_inv);
+
+}  // namespace mppi

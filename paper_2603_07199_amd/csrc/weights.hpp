@@ -1,0 +1,28 @@
+// Device-resident decoder weights, packed once at engine creation.
+//
+// The first layer's coordinate columns (H x 3, padded to 4) and the output
+// row stay float32 for the vector units; the first layer's latent block is
+// folded per solve into a bias (W1[:, 3:] z + b1), an exact re-association of
+// the concatenated input [p; z] of Section III-B.  Hidden H x H layers are
+// packed in matrix-core operand order for the chosen precision.
+#pragma once
+#include <stdint.h>
+
+namespace mppi {
+
+struct DeviceWeights {
+  int H, n_hidden, precision;
+  const float* w1p;      // H x 4: W1[:, 0..2], 0
+  const float* hbias;    // (n_hidden - 1) x H
+  const float* wout;     // H
+  float bout;
+  // FP32: per hidden layer, fragments [mb][ks][64] of W[16 mb + lane%16][4 ks + lane/16]
+  const float* hidden_f32;
+  // BF16 family / FP8: per hidden layer, per wave slice, see kernels_mfma.hip
+  const void* hidden_lp;
+  const float* w_scale;  // FP8: per hidden layer weight scale
+  const float* a_scale;  // FP8: per hidden layer activation scale
+  const float* a_inv;    // FP8: 1 / a_scale
+};
+
+}  // namespace mppi

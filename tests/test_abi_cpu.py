@@ -1,0 +1,186 @@
+"""C ABI checks that need no GPU: the library loads and exports every function
+declared in include/mppi.h, the ctypes structures match the C layout, status
+strings, create() without a usable device, and the host-only engine logic
+(arena, admission queue, solve layout) in a g++-built test driver."""
+import ctypes as C
+import os
+import re
+import shutil
+import subprocess
+
+import pytest
+
+from paper_2603_07199_amd import mppi as M
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mppi.h")
+CSRC = os.path.join(ROOT, "paper_2603_07199_amd", "csrc")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:[\w\s\*]+?)\b(mppi_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_library_exports_every_declared_function():
+    lib = M.load_library()
+    names = _declared_functions()
+    assert "mppi_create" in names and "mppi_poll" in names
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(M.EXPORTED) == names
+
+
+def test_status_strings():
+    assert M.status_str(0) == "ok"
+    assert "invalid" in M.status_str(-1)
+    assert M.status_str(12345) == "unknown status"
+
+
+@pytest.fixture(scope="module")
+def layout_probe(tmp_path_factory):
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("gcc missing")
+    d = tmp_path_factory.mktemp("abi")
+    src = d / "probe.c"
+    structs = {
+        "mppi_config": M.mppi_config, "mppi_sdf_weights": M.mppi_sdf_weights,
+        "mppi_gate": M.mppi_gate, "mppi_request": M.mppi_request,
+        "mppi_result": M.mppi_result, "mppi_stats": M.mppi_stats,
+    }
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void){"]
+    for cname, cls in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in cls._fields_:
+            cf = "lambda" if f == "lambda_" else f
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {cf}));')
+    lines.append("return 0;}")
+    src.write_text("\n".join(lines))
+    exe = d / "probe"
+    subprocess.run([gcc, "-std=c11", str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout
+    table = {}
+    for line in out.splitlines():
+        s, f, v = line.split()
+        table[(s, f)] = int(v)
+    return structs, table
+
+
+def test_ctypes_layout_matches_header(layout_probe):
+    structs, table = layout_probe
+    for cname, cls in structs.items():
+        assert C.sizeof(cls) == table[(cname, "size")], cname
+        for f, _ in cls._fields_:
+            assert getattr(cls, f).offset == table[(cname, f)], (cname, f)
+
+
+def test_create_rejects_bad_config_or_reports_no_device():
+    import scenarios as sc
+    cfg = M.default_config(sc.MODEL)
+    cfg["latent_dim"] = 32
+    with pytest.raises(M.MPPIError) as e:
+        M.mppi_create(cfg, None)
+    assert e.value.code == M.MPPI_EINVAL
+    cfg = M.default_config(sc.MODEL, sdf_kind="analytic")
+    try:
+        import torch
+        has_gpu = torch.cuda.is_available()
+    except Exception:
+        has_gpu = False
+    if not has_gpu:
+        with pytest.raises(M.MPPIError) as e:
+            M.mppi_create(cfg, None)
+        assert e.value.code == M.MPPI_EDEVICE
+
+
+HOST_TEST = r"""
+#include <cassert>
+#include <cstdio>
+#include <random>
+#include <vector>
+#include "host_core.hpp"
+using namespace mppi;
+int main() {
+  // arena: alloc/free/coalesce, alignment, exhaustion
+  Arena a(1 << 20);
+  uint64_t o1, o2, o3;
+  assert(a.alloc(1000, &o1) && o1 == 0);
+  assert(a.alloc(5000, &o2) && o2 == 1024);
+  assert(a.alloc(1, &o3) && o3 == 1024 + 5120);
+  assert(a.in_use() == 1024 + 5120 + 256);
+  a.release(o2, 5000);
+  uint64_t o4;
+  assert(a.alloc(4000, &o4) && o4 == 1024);       // first fit reuses the hole
+  a.release(o1, 1000); a.release(o4, 4000); a.release(o3, 1);
+  assert(a.in_use() == 0 && a.fragments() == 1 && a.largest_free() == (1u << 20));
+  uint64_t big;
+  assert(!a.alloc((1 << 20) + 1, &big));
+  std::mt19937 rng(3);
+  std::vector<std::pair<uint64_t, uint64_t>> live;
+  for (int i = 0; i < 20000; ++i) {
+    if (live.empty() || (rng() % 3)) {
+      uint64_t sz = 1 + rng() % 20000, off;
+      if (a.alloc(sz, &off)) {
+        for (auto& l : live) assert(off + align_up(sz) <= l.first || l.first + align_up(l.second) <= off);
+        live.push_back({off, sz});
+      }
+    } else {
+      size_t j = rng() % live.size();
+      a.release(live[j].first, live[j].second);
+      live.erase(live.begin() + j);
+    }
+  }
+  for (auto& l : live) a.release(l.first, l.second);
+  assert(a.in_use() == 0 && a.fragments() == 1);
+  // admission: FIFO, budget, in-flight cap, busy instances, never-fits
+  Admission q(1000, 2, 4);
+  assert(q.push({1, 10, 400}) == 0);
+  assert(q.push({2, 11, 700}) == 0);
+  assert(q.push({3, 12, 100}) == 0);
+  assert(q.push({4, 13, 1001}) == -2);
+  assert(q.push({5, 10, 100}) == 0);
+  assert(q.push({6, 14, 100}) == -3);             // depth 4 reached
+  auto none = [](uint64_t) { return false; };
+  auto adm = q.admit(none);
+  assert(adm.size() == 1 && adm[0].ticket == 1);  // 2 does not fit, 3 may not overtake it
+  q.complete(400);
+  adm = q.admit(none);
+  assert(adm.size() == 2 && adm[0].ticket == 2 && adm[1].ticket == 3);  // 700 + 100 fit
+  adm = q.admit(none);
+  assert(adm.empty());                            // in-flight cap of 2
+  q.complete(700); q.complete(100);
+  adm = q.admit([](uint64_t id) { return id == 10; });
+  assert(adm.empty());                            // instance 10 busy
+  adm = q.admit(none);
+  assert(adm.size() == 1 && adm[0].ticket == 5);
+  q.complete(100);
+  // same instance twice in one pass: only the first is admitted
+  Admission q2(1000, 8, 8);
+  q2.push({7, 1, 10}); q2.push({8, 1, 10}); q2.push({9, 2, 10});
+  adm = q2.admit(none);
+  assert(adm.size() == 2 && adm[0].ticket == 7 && adm[1].ticket == 9);
+  // layout: regions are disjoint, aligned, and grow with K, T, G
+  SolveLayout L = solve_layout(4096, 50, 4, 256, false, 0);
+  assert(L.total % kAlign == 0 && L.upload_bytes <= L.result);
+  assert(L.samples >= L.result && L.total >= L.samples + 4ull * 4 * 50 * 4096);
+  SolveLayout F = solve_layout(4096, 50, 4, 256, true, 256);
+  assert(F.total < L.total);
+  std::printf("HOST OK\n");
+  return 0;
+}
+"""
+
+
+def test_host_core_logic(tmp_path):
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("g++ missing")
+    src = tmp_path / "t.cpp"
+    src.write_text(HOST_TEST)
+    exe = tmp_path / "t"
+    subprocess.run([gxx, "-std=c++17", "-O1", "-g", "-fsanitize=address,undefined",
+                    "-I", CSRC, str(src), "-o", str(exe)], check=True)
+    r = subprocess.run([str(exe)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    assert "HOST OK" in r.stdout
