@@ -1,0 +1,185 @@
+"""Benchmark: MPPI solves of the paper-scale workload on one MI355X.
+
+Workload (one step = one MPPI iteration of every staged request): K = 4096
+rollouts, horizon T = 50 (dt = 0.02 s), 4 gates, Gate-SDF decoder
+67 -> 256 -> 256 -> 256 -> 1, seeded synthetic inputs (see scenarios/).
+The requests are staged into device memory before timing (mppi_batch_*), so
+the timed region holds kernel launches only; each instance's warm start and
+RNG tick advance on the device from step to step.
+
+Prints one JSON line: rollout-steps/s (value), per-step latency p50/p99, the
+roofline of the dominant kernel (HIP-event durations recorded by the library
+on its own stream), the FP32 plain one-solve-per-launch path on the same
+workload for comparison, and the FP64 oracle timed on the host cores.
+
+    python bench.py [--steps K] [--warmup W] [--path fused|plain]
+                    [--precision bf16x2|bf16|fp8|fp32] [--batch B]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import scenarios as sc  # noqa: E402
+
+HBM_PEAK = 8.0e12
+PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "bf16x2": 2500.0, "fp8": 5000.0}
+LAYERS = (67, 256, 256, 256, 1)
+K_, T_, G_ = 4096, 50, 4
+KERNEL_SOURCES = {"plain": "kernels_plain.hip", "fused": "kernels_fused.hip"}
+
+
+def _problems(n, M):
+    return [sc.config_problem("P2", 1 + i, instance_id=10_000 + i, tick=M.TICK_RESIDENT)
+            for i in range(n)]
+
+
+def _mfma_flops_per_query(layers):
+    H = layers[1]
+    n_hh = len(layers) - 3          # H x H layers
+    return 2.0 * n_hh * H * H
+
+
+def _source_hash(path):
+    full = os.path.join(ROOT, "paper_2603_07199_amd", "csrc", KERNEL_SOURCES[path])
+    with open(full, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def _traffic(path, precision, launches_queries):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
+    counter summary, or None when absent or taken on a different kernel."""
+    f = os.path.join(ROOT, "profiles", f"traffic_{path}_{precision}_p2.json")
+    if not os.path.exists(f):
+        return None
+    with open(f) as fh:
+        t = json.load(fh)
+    if t.get("source_sha256_16") != _source_hash(path):
+        return None
+    return float(t["bytes_per_launch"])
+
+
+def run_leg(M, path, precision, batch, steps, warmup):
+    W, b = sc.config_weights("P2")
+    probs = _problems(batch, M)
+    eng = M.Engine((W, b), sc.MODEL, K_max=K_, T_max=T_, G_max=G_, hidden=LAYERS[1],
+                   n_hidden=len(LAYERS) - 2, precision=precision, path=path,
+                   budget=2 << 30, timing=True, max_instances=max(64, batch))
+    bt = eng.batch(probs)
+    for _ in range(warmup):
+        bt.run()
+        bt.wait()
+    eng.reset_stats()
+    lat = []
+    t_start = time.perf_counter()
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        bt.run()
+        bt.wait()
+        lat.append(time.perf_counter() - t0)
+    elapsed = time.perf_counter() - t_start
+    st = eng.stats()
+    res = bt.results()
+    bt.close()
+    eng.close()
+    for r in res:
+        if r["status"] != 0:
+            raise RuntimeError(f"solve failed with status {r['status']}")
+    rs = batch * K_ * T_ * steps
+    return {
+        "rollout_steps_per_s": rs / elapsed,
+        "ms_per_step": 1e3 * elapsed / steps,
+        "lat_ms": np.array(lat) * 1e3,
+        "sdf_ms": st["sdf_ms"] / max(st["sdf_launches"], 1),
+        "sdf_launches": st["sdf_launches"],
+        "solve_ms": st["solve_ms"] / max(st["solve_launches"], 1),
+    }
+
+
+def cpu_baseline():
+    """The FP64 oracle on one full paper-scale solve (K = 4096, T = 50, G = 4)."""
+    import torch
+
+    import oracle
+    W, b = sc.config_weights("P2")
+    prob = sc.config_problem("P2", 1)
+    t0 = time.perf_counter()
+    oracle.solve(prob, (W, b), sc.MODEL)
+    dt = time.perf_counter() - t0
+    return {"value": K_ * T_ / dt, "unit": "rollout-steps/s", "cores": int(torch.get_num_threads()),
+            "kind": "oracle",
+            "sample": f"one full solve of the workload (K={K_}, T={T_}, G={G_}, "
+                      f"67-256-256-256-1 decoder) in float64: {dt:.2f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--path", default="plain", choices=["plain", "fused"])
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "bf16x2", "fp8"])
+    ap.add_argument("--batch", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-compare", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build shards nothing across GPUs "
+              "(see DESIGN.md for how the path would shard); run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+    from paper_2603_07199_amd import mppi as M
+    M.load_library()
+
+    main_leg = run_leg(M, args.path, args.precision, args.batch, args.steps, args.warmup)
+    queries = args.batch * K_ * T_ * G_
+    flops = _mfma_flops_per_query(LAYERS) * queries          # per launch of the dominant kernel
+    achieved = flops / (main_leg["sdf_ms"] * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[args.precision]
+    traffic = _traffic(args.path, args.precision, queries)
+    out = {
+        "metric": "rollout-steps/s and p50/p99 solve latency, BF16-served vs FP32-plain MPPI",
+        "value": main_leg["rollout_steps_per_s"],
+        "unit": "rollout-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_leg["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp32": "f32", "bf16": "bf16", "bf16x2": "bf16x2", "fp8": "fp8"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": f"MPPI solve K={K_} T={T_} dt=0.02 G={G_} decoder 67-256-256-256-1",
+                   "path": args.path, "precision": args.precision, "solves_per_step": args.batch,
+                   "parallelism": "single-gpu"},
+        "latency_ms": {"p50": float(np.percentile(main_leg["lat_ms"], 50)),
+                       "p99": float(np.percentile(main_leg["lat_ms"], 99))},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": traffic,
+                     "kernel": "k_sdf_f32" if args.path == "plain" else "k_fused",
+                     "kernel_ms": main_leg["sdf_ms"],
+                     "algorithmic_flops_per_launch": flops},
+    }
+    if not args.no_compare and not (args.path == "plain" and args.precision == "fp32"):
+        ref = run_leg(M, "plain", "fp32", 1, max(3, args.steps // 4), 1)
+        out["fp32_plain"] = {"rollout_steps_per_s": ref["rollout_steps_per_s"],
+                             "ms_per_step": ref["ms_per_step"],
+                             "speedup": main_leg["rollout_steps_per_s"] / ref["rollout_steps_per_s"]}
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

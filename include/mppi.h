@@ -211,6 +211,24 @@ const char* mppi_status_str(int status);
  * of budget admission). */
 uint64_t mppi_solve_footprint(const mppi_engine* engine, int32_t K, int32_t T, int32_t G);
 
+/* Staged batches: n requests validated, packed and copied into device memory
+ * once, then launched any number of times with their inputs resident in HBM
+ * (a fixed fleet ticking, or a benchmark).  Each launch is one MPPI iteration
+ * (Section IV-A) of every request; requests with U_nom == NULL and
+ * tick == MPPI_TICK_RESIDENT advance their resident warm start and tick on
+ * the device at every launch.  Instance ids within a batch must be distinct
+ * (EINVAL otherwise) and are held until mppi_batch_destroy (EAGAIN for other
+ * calls on them meanwhile).  ENOMEM if the per-solve buffers do not fit.
+ * Launches are asynchronous on the engine's stream; mppi_batch_wait blocks
+ * until they finish; mppi_batch_results copies the latest outcome of request
+ * i into results[i] (caller-owned, U_star sized T_i x 4). */
+typedef struct mppi_batch mppi_batch;
+int mppi_batch_create(mppi_engine* engine, const mppi_request* requests, int32_t n, mppi_batch** out);
+int mppi_batch_run(mppi_engine* engine, mppi_batch* batch);
+int mppi_batch_wait(mppi_engine* engine, mppi_batch* batch);
+int mppi_batch_results(mppi_engine* engine, mppi_batch* batch, mppi_result* results);
+int mppi_batch_destroy(mppi_engine* engine, mppi_batch* batch);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,16 +1,24 @@
 // MPPI engine: the C ABI of include/mppi.h.
 //
-// Host work per solve (done in float64, then rounded once to float32):
+// Host work per solve (float64, then rounded once to float32):
 //  - validation of the request;
 //  - L = chol(Sigma) for delta u = L n (Section IV-A: delta u ~ N(0, Sigma));
-//  - the latent fold c_g = W1[:, 3:] z_g + b1 (exact re-association of the
-//    decoder input [p; z], Section III-B / Fig. 2);
-//  - gate frames: R_g^T and the offsets of the local rollout frame, so a
-//    device position dp (relative to p0 + v0 t dt) maps to the gate frame as
-//    R_g^T dp + base_g(t);
+//  - gate frames: R_g^T and the offsets of the local rollout frame, so that a
+//    device position dp (relative to p0 + v0 t dt) maps into gate g's frame
+//    as R_g^T dp + base_g(t) (Section IV-B-3: world points are mapped into the
+//    cached gate/camera frame before the decoder is queried);
 //  - the rollout-independent part of the progress cost (eq. 5), which cancels
 //    in the weights (eq. mppi_update) and is added back to reported costs.
-// Everything else runs in the device kernels.
+// Everything else, including the latent fold of the decoder's first layer,
+// runs in the device kernels.
+//
+// Three ways to run solves share one staging routine and one launch routine:
+//  - mppi_step: one blocking solve;
+//  - mppi_submit / mppi_poll: a scheduler thread admits queued requests by
+//    device-memory budget, batches what is admissible and launches each batch
+//    on a free stream while earlier batches still run (continuous batching);
+//  - mppi_batch_*: requests staged once into device memory and launched
+//    repeatedly (fixed fleets, benchmarks): inputs stay resident in HBM.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <string.h>
@@ -24,6 +32,7 @@
 #include <mutex>
 #include <thread>
 #include <unordered_map>
+#include <unordered_set>
 #include <vector>
 
 #include "../../include/mppi.h"
@@ -46,8 +55,8 @@ bool isfin(double x) { return std::isfinite(x); }
 
 struct InstInfo {
   uint64_t id;
-  int U_len;      // entries of the resident sequence that are valid
-  bool busy;      // a served solve of this instance is queued or in flight
+  int U_len;      // valid entries of the resident sequence
+  bool busy;      // a served solve or a staged batch holds this instance
 };
 
 // Deep copy of a request for the served path.
@@ -62,17 +71,18 @@ struct OwnedRequest {
       U.assign(r.U_nom, r.U_nom + 4 * (size_t)r.T);
       req.U_nom = U.data();
     }
-    z.resize((size_t)r.G * latent);
-    gates.assign(r.gates, r.gates + r.G);
-    for (int g = 0; g < r.G; ++g) {
-      memcpy(&z[(size_t)g * latent], r.gates[g].z, sizeof(float) * latent);
+    const int G = r.G > 0 && r.gates ? r.G : 0;
+    z.assign((size_t)G * latent, 0.0f);
+    gates.assign(r.gates, r.gates + G);
+    for (int g = 0; g < G; ++g) {
+      if (r.gates[g].z) memcpy(&z[(size_t)g * latent], r.gates[g].z, sizeof(float) * latent);
       gates[g].z = &z[(size_t)g * latent];
     }
     req.gates = gates.data();
   }
 };
 
-// One solve living on the device.
+// One solve living in device memory.
 struct Solve {
   uint64_t ticket = 0;
   int K = 0, T = 0, G = 0;
@@ -84,22 +94,33 @@ struct Solve {
   double C0 = 0.0;
   double v0[3] = {0, 0, 0};
   double dt = 0.0;
-  bool exports = false;
+  bool exports = false, want_w = true, want_J = true;
   uint64_t t_submit = 0, t_admit = 0, t_done = 0;
-  // host result copies
-  std::vector<double> res;       // 4T + RES_SCALARS
-  std::vector<double> wn;        // K
-  std::vector<float> J;          // K
+  std::vector<double> res;   // 4T + RES_SCALARS
+  std::vector<double> wn;    // K
+  std::vector<float> J;      // K
   std::vector<float> samples, pos, sdf;
-  bool want_w = false, want_J = false;
 };
 
-struct Batch {
+// Device arrays of a fused launch: descriptors, tile list, work counter.
+struct Aux {
+  uint64_t off = 0, bytes = 0;
+  const SolveDesc* descs = nullptr;
+  const int2* tiles = nullptr;
+  uint32_t* counter = nullptr;
+  int n_tiles = 0, maxT = 1, maxG = 1;
+};
+
+struct Staged {
   std::vector<std::unique_ptr<Solve>> solves;
+  Aux aux;
+};
+
+struct Inflight {
+  Staged st;
   hipEvent_t done = nullptr;
+  hipEvent_t t0 = nullptr, t1 = nullptr;
   int stream_idx = 0;
-  // fused path device arrays
-  uint64_t aux_off = 0, aux_bytes = 0;
 };
 
 }  // namespace
@@ -108,41 +129,40 @@ struct mppi_engine {
   mppi_config cfg{};
   int H = 0, L = 0;
   int dev = 0;
-  std::vector<hipStream_t> streams;   // [0] = blocking path; others for the served path
+  bool fused = false;
+  std::vector<hipStream_t> streams;   // [0]: blocking path and batches; 1..: served batches
   bool own_stream0 = false;
   char* pool = nullptr;
   uint64_t pool_bytes = 0;
   bool own_pool = false;
   Arena arena;
-  // weights
   void* wmem = nullptr;
   DeviceWeights dw{};
-  std::vector<double> W0lat;   // H x latent (float32 values)
-  std::vector<double> b0;      // H
-  // instance table
-  double* instU = nullptr;     // max_instances x T_max x 4
+  double* instU = nullptr;      // max_instances x T_max x 4
   uint32_t* instTick = nullptr;
   std::unordered_map<uint64_t, int> inst_map;
   std::vector<InstInfo> inst;
-  std::vector<double> hover_host;   // T_max x 4, pinned copy below
-  double* hover_pinned = nullptr;
-  // staging for the blocking path
-  char* stage = nullptr;       // pinned, max upload bytes
-  uint64_t stage_bytes = 0;
+  std::vector<double> hover;    // T_max x 4
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   mppi_stats stats{};
   std::atomic<int> sticky{0};
-  std::mutex mu;               // guards everything above
+  std::mutex mu;                // guards everything above and below
   // served path
   std::thread sched;
   std::condition_variable cv;
   bool stop = false;
   std::unique_ptr<Admission> adm;
   uint64_t next_ticket = 1;
-  std::unordered_map<uint64_t, OwnedRequest> pending;          // queued requests
-  std::vector<Batch> inflight;
-  std::unordered_map<uint64_t, std::unique_ptr<Solve>> done;   // finished, not yet polled
+  std::unordered_map<uint64_t, OwnedRequest> pending;
+  std::vector<Inflight> inflight;
+  std::unordered_map<uint64_t, std::unique_ptr<Solve>> done;
   std::unordered_map<uint64_t, uint64_t> ticket_submit_ns;
+};
+
+struct mppi_batch {
+  Staged st;
+  hipEvent_t t0 = nullptr, t1 = nullptr, s0 = nullptr, s1 = nullptr;
+  bool launched = false;
 };
 
 namespace {
@@ -155,9 +175,9 @@ int dev_fail(mppi_engine* e, hipError_t err) {
   return MPPI_OK;
 }
 
-#define HIPCHK(e, x)                                  \
-  do {                                                \
-    hipError_t err_ = (x);                            \
+#define HIPCHK(e, x)                                    \
+  do {                                                  \
+    hipError_t err_ = (x);                              \
     if (err_ != hipSuccess) return dev_fail((e), err_); \
   } while (0)
 
@@ -216,26 +236,25 @@ int validate(const mppi_engine* e, const mppi_request* r, double Lo[16]) {
   const double qn = sqrt(r->x0[3] * r->x0[3] + r->x0[4] * r->x0[4] + r->x0[5] * r->x0[5] +
                          r->x0[6] * r->x0[6]);
   if (fabs(qn - 1.0) > 1e-6) return MPPI_EINVAL;
-  const double w[6] = {r->Q_gate, r->Q_vis, r->Q_sdf, r->d_safe, r->R_u, 0.0};
-  for (int i = 0; i < 5; ++i)
-    if (std::isnan(w[i])) return MPPI_EINVAL;
+  const double wts[5] = {r->Q_gate, r->Q_vis, r->Q_sdf, r->d_safe, r->R_u};
+  for (double v : wts)
+    if (std::isnan(v)) return MPPI_EINVAL;
   if (!isfin(r->d_safe)) return MPPI_EINVAL;
   for (int i = 0; i < 3; ++i)
     if (!isfin(r->wp[i])) return MPPI_EINVAL;
   if (r->U_nom)
     for (int i = 0; i < 4 * r->T; ++i)
       if (!isfin(r->U_nom[i])) return MPPI_EINVAL;
-  {
-    if (!r->gates) return MPPI_EINVAL;
-    for (int g = 0; g < r->G; ++g) {
-      if (c.sdf_kind == MPPI_SDF_MLP && !r->gates[g].z) return MPPI_EINVAL;
-      for (int i = 0; i < 9; ++i)
-        if (!isfin(r->gates[g].R[i])) return MPPI_EINVAL;
-      for (int i = 0; i < 3; ++i)
-        if (!isfin(r->gates[g].t[i])) return MPPI_EINVAL;
-      if (c.sdf_kind == MPPI_SDF_MLP)
-        for (int i = 0; i < c.latent_dim; ++i)
-          if (!std::isfinite(r->gates[g].z[i])) return MPPI_EINVAL;
+  if (!r->gates) return MPPI_EINVAL;
+  for (int g = 0; g < r->G; ++g) {
+    for (int i = 0; i < 9; ++i)
+      if (!isfin(r->gates[g].R[i])) return MPPI_EINVAL;
+    for (int i = 0; i < 3; ++i)
+      if (!isfin(r->gates[g].t[i])) return MPPI_EINVAL;
+    if (c.sdf_kind == MPPI_SDF_MLP) {
+      if (!r->gates[g].z) return MPPI_EINVAL;
+      for (int i = 0; i < c.latent_dim; ++i)
+        if (!std::isfinite(r->gates[g].z[i])) return MPPI_EINVAL;
     }
   }
   return cholesky4(r->Sigma, Lo);
@@ -250,27 +269,29 @@ int acquire_slot(mppi_engine* e, uint64_t id, int* slot) {
   }
   if ((int)e->inst.size() >= e->cfg.max_instances) return MPPI_EAGAIN;
   const int s = (int)e->inst.size();
+  // a new instance starts from hover with tick 0 (ticks are zeroed at create)
+  HIPCHK(e, hipMemcpy(e->instU + (size_t)s * e->cfg.T_max * 4, e->hover.data(),
+                      sizeof(double) * 4 * e->cfg.T_max, hipMemcpyHostToDevice));
   e->inst.push_back(InstInfo{id, e->cfg.T_max, false});
   e->inst_map[id] = s;
-  // a new instance starts from hover with tick 0 (ticks were zeroed at create)
-  HIPCHK(e, hipMemcpyAsync(e->instU + (size_t)s * e->cfg.T_max * 4, e->hover_pinned,
-                           sizeof(double) * 4 * e->cfg.T_max, hipMemcpyHostToDevice,
-                           e->streams[0]));
-  HIPCHK(e, hipStreamSynchronize(e->streams[0]));
   *slot = s;
   return MPPI_OK;
 }
 
-uint64_t footprint_of(const mppi_engine* e, int K, int T, int G, bool fused) {
-  const int R = fused ? fused_tile_rollouts(e->cfg.precision, e->H, G) : 1;
-  const int nt = fused ? (K + R - 1) / R : 0;
-  return solve_layout(K, T, G, e->H, fused, nt).total;
+int tile_rollouts(const mppi_engine* e, int G) {
+  return fused_tile_rollouts(e->cfg.precision, e->H, G);
+}
+
+SolveLayout layout_for(const mppi_engine* e, int K, int T, int G) {
+  const int R = e->fused ? tile_rollouts(e, G) : 1;
+  const int nt = e->fused ? (K + R - 1) / R : 0;
+  return solve_layout(K, T, G, e->H, e->fused, nt);
 }
 
 // Fill the upload part (descriptor + request data) of a solve whose device
 // block starts at `base`.  Lo is the Cholesky factor from validate().
 void pack_solve(mppi_engine* e, const mppi_request* r, Solve* s, const double Lo[16], char* base,
-                char* host, bool fused, int tile_R) {
+                char* host) {
   const mppi_config& c = e->cfg;
   const int K = r->K, T = r->T, G = r->G, H = e->H;
   const SolveLayout& lay = s->lay;
@@ -309,19 +330,18 @@ void pack_solve(mppi_engine* e, const mppi_request* r, Solve* s, const double Lo
   const double* p0 = r->x0;
   const double* v0 = r->x0 + 7;
   const double tau = T * r->dt;
-  double e_[3], vt[3];
+  double ev[3], vt[3];
   for (int i = 0; i < 3; ++i) {
-    e_[i] = p0[i] - r->wp[i];
+    ev[i] = p0[i] - r->wp[i];
     vt[i] = v0[i] * tau;
-    d.fprog[i] = (float)(vt[i] + e_[i]);
+    d.fprog[i] = (float)(vt[i] + ev[i]);
   }
   const double qg = r->Q_gate;
   const double c0 = vt[0] * vt[0] + vt[1] * vt[1] + vt[2] * vt[2] +
-                    2.0 * (vt[0] * e_[0] + vt[1] * e_[1] + vt[2] * e_[2]);
+                    2.0 * (vt[0] * ev[0] + vt[1] * ev[1] + vt[2] * ev[2]);
   d.C0 = (qg == 0.0 || c0 == 0.0) ? 0.0 : qg * c0;
   s->C0 = d.C0;
   d.hover[0] = c.mass * c.gravity;
-  // nominal sequence: the request's copy, else the resident slot
   if (r->U_nom) {
     memcpy(host + lay.U, r->U_nom, sizeof(double) * 4 * T);
     d.U_src = (const double*)(base + lay.U);
@@ -332,10 +352,9 @@ void pack_solve(mppi_engine* e, const mppi_request* r, Solve* s, const double Lo
   }
   d.U_resident = e->instU + (size_t)s->slot * c.T_max * 4;
   d.tick_slot = e->instTick + s->slot;
-  // gates
   float* Rt = (float*)(host + lay.Rt);
   float* bs = (float*)(host + lay.base);
-  float* cf = (float*)(host + lay.cfold);
+  float* zz = (float*)(host + lay.z);
   for (int g = 0; g < G; ++g) {
     const double* R = r->gates[g].R;
     const double* tg = r->gates[g].t;
@@ -353,16 +372,9 @@ void pack_solve(mppi_engine* e, const mppi_request* r, Solve* s, const double Lo
       }
     }
     for (int t = 0; t <= T; ++t)
-      for (int i = 0; i < 3; ++i) bs[((size_t)g * (T + 1) + t) * 3 + i] = (float)(o[i] + (t * r->dt) * rv[i]);
-    if (c.sdf_kind == MPPI_SDF_MLP) {
-      const float* z = r->gates[g].z;
-      for (int m = 0; m < H; ++m) {
-        double acc = e->b0[m];
-        const double* wr = &e->W0lat[(size_t)m * c.latent_dim];
-        for (int j = 0; j < c.latent_dim; ++j) acc += wr[j] * (double)z[j];
-        cf[(size_t)g * H + m] = (float)acc;
-      }
-    }
+      for (int i = 0; i < 3; ++i)
+        bs[((size_t)g * (T + 1) + t) * 3 + i] = (float)(o[i] + (t * r->dt) * rv[i]);
+    if (c.sdf_kind == MPPI_SDF_MLP) memcpy(zz + (size_t)g * kLatent, r->gates[g].z, sizeof(float) * kLatent);
   }
   float* los = (float*)(host + lay.los);
   for (int t = 0; t < T; ++t) {
@@ -371,29 +383,178 @@ void pack_solve(mppi_engine* e, const mppi_request* r, Solve* s, const double Lo
   }
   d.Rt = (const float*)(base + lay.Rt);
   d.base = (const float*)(base + lay.base);
-  d.cfold = (const float*)(base + lay.cfold);
+  d.z = (const float*)(base + lay.z);
+  d.cfold = (float*)(base + lay.cfold);
   d.los = (const float*)(base + lay.los);
   d.result = (double*)(base + lay.result);
   d.J = (float*)(base + lay.J);
   d.wn = s->want_w ? (double*)(base + lay.wn) : nullptr;
-  if (!fused) {
+  if (!e->fused) {
     d.samples = (float*)(base + lay.samples);
     d.pos = (float*)(base + lay.pos);
     d.sdf = (float*)(base + lay.sdf);
     d.Jpart = (float*)(base + lay.Jpart);
     d.wt = (double*)(base + lay.wt);
   } else {
+    const int R = tile_rollouts(e, G);
     d.partials = (double*)(base + lay.partials);
     d.tiles_done = (uint32_t*)(base + lay.tiles_done);
-    d.tile_rollouts = tile_R;
-    d.n_tiles = (K + tile_R - 1) / tile_R;
+    d.tile_rollouts = R;
+    d.n_tiles = (K + R - 1) / R;
   }
   memcpy(host + lay.desc, &d, sizeof(SolveDesc));
   s->dt = r->dt;
   for (int i = 0; i < 3; ++i) s->v0[i] = v0[i];
 }
 
-void fill_result(mppi_engine* e, Solve* s, mppi_result* out) {
+void release_staged(mppi_engine* e, Staged& st, bool free_instances) {
+  for (auto& s : st.solves) {
+    if (!s) continue;
+    if (s->bytes) e->arena.release(s->off, s->bytes);
+    s->bytes = 0;
+    if (free_instances && s->slot >= 0) e->inst[s->slot].busy = false;
+  }
+  if (st.aux.bytes) e->arena.release(st.aux.off, st.aux.bytes);
+  st.aux.bytes = 0;
+}
+
+// Validate, bind instances, allocate, pack and upload a set of requests.
+// Every instance is held busy until the staged set is released.  On failure
+// nothing stays allocated or held.
+int stage(mppi_engine* e, const std::vector<const mppi_request*>& reqs, bool want_w, bool want_J,
+          bool exports, Staged& out) {
+  std::unordered_set<uint64_t> ids;
+  for (auto* r : reqs)
+    if (!ids.insert(r->instance_id).second) return MPPI_EINVAL;   // one solve per instance at a time
+  std::vector<char> host;
+  for (auto* r : reqs) {
+    double Lo[16];
+    int rc = validate(e, r, Lo);
+    auto s = std::make_unique<Solve>();
+    s->K = r->K;
+    s->T = r->T;
+    s->G = r->G;
+    s->flags = r->flags;
+    s->want_w = want_w;
+    s->want_J = want_J;
+    s->exports = exports && !e->fused;
+    if (rc == MPPI_OK) rc = acquire_slot(e, r->instance_id, &s->slot);
+    if (rc == MPPI_OK && e->inst[s->slot].busy) rc = MPPI_EAGAIN;
+    if (rc == MPPI_OK) {
+      s->lay = layout_for(e, r->K, r->T, r->G);
+      if (!e->arena.alloc(s->lay.total, &s->off)) rc = MPPI_ENOMEM;
+      else s->bytes = s->lay.total;
+    }
+    if (rc != MPPI_OK) {
+      release_staged(e, out, true);
+      out.solves.clear();
+      return rc;
+    }
+    e->inst[s->slot].busy = true;
+    host.assign(s->lay.upload_bytes, 0);
+    char* base = e->pool + s->off;
+    pack_solve(e, r, s.get(), Lo, base, host.data());
+    const uint64_t ub = s->lay.upload_bytes;
+    out.solves.push_back(std::move(s));
+    hipError_t err = hipMemcpy(base, host.data(), ub, hipMemcpyHostToDevice);
+    if (err != hipSuccess) {
+      release_staged(e, out, true);
+      out.solves.clear();
+      return dev_fail(e, err);
+    }
+  }
+  if (e->fused) {
+    std::vector<int2> tiles;
+    Aux& a = out.aux;
+    for (size_t i = 0; i < out.solves.size(); ++i) {
+      const Solve* s = out.solves[i].get();
+      const int R = s->desc.tile_rollouts;
+      for (int t = 0; t < s->desc.n_tiles; ++t) tiles.push_back(int2{(int)i, t * R});
+      a.maxT = std::max(a.maxT, s->T);
+      a.maxG = std::max(a.maxG, s->G);
+    }
+    // longest tiles first (work per tile grows with T G); ties keep solve order
+    std::stable_sort(tiles.begin(), tiles.end(), [&](const int2& x, const int2& y) {
+      const Solve* sx = out.solves[x.x].get();
+      const Solve* sy = out.solves[y.x].get();
+      return sx->T * sx->G > sy->T * sy->G;
+    });
+    const size_t nS = out.solves.size();
+    const uint64_t o_tiles = align_up(sizeof(SolveDesc) * nS);
+    const uint64_t o_cnt = o_tiles + align_up(sizeof(int2) * tiles.size());
+    const uint64_t bytes = o_cnt + kAlign;
+    if (!e->arena.alloc(bytes, &a.off)) {
+      release_staged(e, out, true);
+      out.solves.clear();
+      return MPPI_ENOMEM;
+    }
+    a.bytes = bytes;
+    std::vector<char> ah(a.bytes, 0);
+    for (size_t i = 0; i < nS; ++i) memcpy(ah.data() + i * sizeof(SolveDesc), &out.solves[i]->desc, sizeof(SolveDesc));
+    memcpy(ah.data() + o_tiles, tiles.data(), sizeof(int2) * tiles.size());
+    char* ab = e->pool + a.off;
+    hipError_t err = hipMemcpy(ab, ah.data(), a.bytes, hipMemcpyHostToDevice);
+    if (err != hipSuccess) {
+      release_staged(e, out, true);
+      out.solves.clear();
+      return dev_fail(e, err);
+    }
+    a.descs = (const SolveDesc*)ab;
+    a.tiles = (const int2*)(ab + o_tiles);
+    a.counter = (uint32_t*)(ab + o_cnt);
+    a.n_tiles = (int)tiles.size();
+  }
+  return MPPI_OK;
+}
+
+// Enqueue every kernel of a staged set on stream st.  t0/t1 (optional) bracket
+// the dominant kernel(s): the SDF kernels of the plain path, the fused kernel.
+int launch_staged(mppi_engine* e, Staged& sg, hipStream_t st, hipEvent_t t0, hipEvent_t t1) {
+  if (!e->fused) {
+    for (size_t i = 0; i < sg.solves.size(); ++i) {
+      Solve* s = sg.solves[i].get();
+      PlainShape shp{s->K, s->T, s->G, e->cfg.sdf_kind};
+      const bool first = i == 0, last = i + 1 == sg.solves.size();
+      HIPCHK(e, launch_plain((const SolveDesc*)(e->pool + s->off + s->lay.desc), shp, e->dw, st,
+                             first ? t0 : nullptr, last ? t1 : nullptr));
+    }
+    return MPPI_OK;
+  }
+  Aux& a = sg.aux;
+  HIPCHK(e, launch_fold(a.descs, (int)sg.solves.size(), a.maxG, e->dw, st));
+  FusedBatch fb{a.descs, a.tiles, a.n_tiles, a.counter};
+  HIPCHK(e, launch_fused(fb, e->dw, a.maxT, st, t0, t1));
+  return MPPI_OK;
+}
+
+// Enqueue the D2H copies of a solve's outputs on stream st.
+int enqueue_fetch(mppi_engine* e, Solve* s, hipStream_t st) {
+  const int K = s->K, T = s->T;
+  char* base = e->pool + s->off;
+  s->res.resize(4 * T + RES_SCALARS);
+  HIPCHK(e, hipMemcpyAsync(s->res.data(), base + s->lay.result, sizeof(double) * s->res.size(),
+                           hipMemcpyDeviceToHost, st));
+  if (s->want_w) {
+    s->wn.resize(K);
+    HIPCHK(e, hipMemcpyAsync(s->wn.data(), base + s->lay.wn, sizeof(double) * K, hipMemcpyDeviceToHost, st));
+  }
+  if (s->want_J) {
+    s->J.resize(K);
+    HIPCHK(e, hipMemcpyAsync(s->J.data(), base + s->lay.J, sizeof(float) * K, hipMemcpyDeviceToHost, st));
+  }
+  if (s->exports) {
+    s->samples.resize((size_t)4 * T * K);
+    s->pos.resize((size_t)3 * (T + 1) * K);
+    s->sdf.resize((size_t)T * K);
+    HIPCHK(e, hipMemcpyAsync(s->samples.data(), base + s->lay.samples, 4 * s->samples.size(),
+                             hipMemcpyDeviceToHost, st));
+    HIPCHK(e, hipMemcpyAsync(s->pos.data(), base + s->lay.pos, 4 * s->pos.size(), hipMemcpyDeviceToHost, st));
+    HIPCHK(e, hipMemcpyAsync(s->sdf.data(), base + s->lay.sdf, 4 * s->sdf.size(), hipMemcpyDeviceToHost, st));
+  }
+  return MPPI_OK;
+}
+
+void fill_result(const Solve* s, mppi_result* out) {
   const int T = s->T, K = s->K;
   const double* r = s->res.data();
   const double* sc = r + 4 * T;
@@ -404,15 +565,16 @@ void fill_result(mppi_engine* e, Solve* s, mppi_result* out) {
   out->J_min = sc[RES_JMIN];
   out->log_eta = sc[RES_LOGETA];
   out->ess = sc[RES_ESS];
-  if (out->weights && s->want_w) memcpy(out->weights, s->wn.data(), sizeof(double) * K);
-  if (out->costs && s->want_J)
+  if (out->weights && s->want_w && (int)s->wn.size() == K) memcpy(out->weights, s->wn.data(), sizeof(double) * K);
+  if (out->costs && s->want_J && (int)s->J.size() == K)
     for (int k = 0; k < K; ++k) out->costs[k] = (double)s->J[k] + s->C0;
-  if (s->exports) {
+  if (s->exports && !s->samples.empty()) {
     const size_t TK = (size_t)T * K, T1K = (size_t)(T + 1) * K;
     if (out->samples)
       for (int k = 0; k < K; ++k)
         for (int t = 0; t < T; ++t)
-          for (int c = 0; c < 4; ++c) out->samples[((size_t)k * T + t) * 4 + c] = s->samples[c * TK + (size_t)t * K + k];
+          for (int c = 0; c < 4; ++c)
+            out->samples[((size_t)k * T + t) * 4 + c] = s->samples[c * TK + (size_t)t * K + k];
     if (out->positions)
       for (int k = 0; k < K; ++k)
         for (int t = 0; t <= T; ++t)
@@ -426,93 +588,72 @@ void fill_result(mppi_engine* e, Solve* s, mppi_result* out) {
   out->t_submit_ns = s->t_submit;
   out->t_admit_ns = s->t_admit;
   out->t_done_ns = s->t_done;
-  (void)e;
 }
 
-// After a solve's results are on the host: instance bookkeeping.
-void retire_instance(mppi_engine* e, Solve* s) {
-  InstInfo& in = e->inst[s->slot];
+// After a solve's results are on the host: the resident sequence's length.
+void note_result(mppi_engine* e, const Solve* s) {
+  if (s->res.empty() || s->slot < 0) return;
   const int st = (int)s->res[4 * s->T + RES_STATUS];
-  if (st == MPPI_OK && !(s->flags & MPPI_REQ_NO_SHIFT)) in.U_len = s->T;
-  in.busy = false;
+  if (st == MPPI_OK && !(s->flags & MPPI_REQ_NO_SHIFT)) e->inst[s->slot].U_len = s->T;
 }
 
-// Enqueue the D2H copies of a solve's outputs on stream st.
-int enqueue_fetch(mppi_engine* e, Solve* s, hipStream_t st) {
-  const int K = s->K, T = s->T;
-  char* base = e->pool + s->off;
-  s->res.resize(4 * T + RES_SCALARS);
-  HIPCHK(e, hipMemcpyAsync(s->res.data(), base + s->lay.result, sizeof(double) * s->res.size(),
-                           hipMemcpyDeviceToHost, st));
-  if (s->want_w) {
-    s->wn.resize(K);
-    HIPCHK(e, hipMemcpyAsync(s->wn.data(), base + s->lay.wn, sizeof(double) * K,
-                             hipMemcpyDeviceToHost, st));
+void add_time(mppi_engine* e, hipEvent_t a, hipEvent_t b, bool sdf) {
+  float ms = 0.0f;
+  if (a && b && hipEventElapsedTime(&ms, a, b) == hipSuccess) {
+    if (sdf) {
+      e->stats.sdf_ms += ms;
+      e->stats.sdf_launches++;
+    } else {
+      e->stats.solve_ms += ms;
+      e->stats.solve_launches++;
+    }
   }
-  if (s->want_J) {
-    s->J.resize(K);
-    HIPCHK(e, hipMemcpyAsync(s->J.data(), base + s->lay.J, sizeof(float) * K,
-                             hipMemcpyDeviceToHost, st));
-  }
-  if (s->exports) {
-    s->samples.resize((size_t)4 * T * K);
-    s->pos.resize((size_t)3 * (T + 1) * K);
-    s->sdf.resize((size_t)T * K);
-    HIPCHK(e, hipMemcpyAsync(s->samples.data(), base + s->lay.samples, 4 * s->samples.size(),
-                             hipMemcpyDeviceToHost, st));
-    HIPCHK(e, hipMemcpyAsync(s->pos.data(), base + s->lay.pos, 4 * s->pos.size(),
-                             hipMemcpyDeviceToHost, st));
-    HIPCHK(e, hipMemcpyAsync(s->sdf.data(), base + s->lay.sdf, 4 * s->sdf.size(),
-                             hipMemcpyDeviceToHost, st));
-  }
-  return MPPI_OK;
 }
 
 // ---------------------------------------------------------------- weights
 int upload_weights(mppi_engine* e, const mppi_sdf_weights* w) {
   const int H = e->H, L = e->L, D = e->cfg.latent_dim;
-  const int nh = L - 1;  // hidden H x H layers
+  const int nh = std::max(L - 1, 1);  // hidden H x H layers
   const bool mlp = e->cfg.sdf_kind == MPPI_SDF_MLP;
-  // host staging of every device array
-  std::vector<float> w1p((size_t)H * 4, 0.0f), hbias((size_t)std::max(nh, 1) * H, 0.0f),
-      wout(H, 0.0f);
+  std::vector<float> w1p((size_t)H * 4, 0.0f), hbias((size_t)nh * H, 0.0f), wout(H, 0.0f);
+  std::vector<double> w0lat((size_t)H * D, 0.0), b0(H, 0.0);
   std::vector<float> hf32;
   std::vector<uint8_t> hlp;
-  std::vector<float> wsc(std::max(nh, 1), 1.0f), asc(std::max(nh, 1), 1.0f), ainv(std::max(nh, 1), 1.0f);
+  std::vector<float> wsc(nh, 1.0f), asc(nh, 1.0f), ainv(nh, 1.0f);
   float bout = 0.0f;
-  e->W0lat.assign((size_t)H * D, 0.0);
-  e->b0.assign(H, 0.0);
   if (mlp) {
     for (int m = 0; m < H; ++m) {
       for (int i = 0; i < 3; ++i) w1p[m * 4 + i] = w->W[0][(size_t)m * (3 + D) + i];
-      for (int j = 0; j < D; ++j) e->W0lat[(size_t)m * D + j] = w->W[0][(size_t)m * (3 + D) + 3 + j];
-      e->b0[m] = w->b[0][m];
+      for (int j = 0; j < D; ++j) w0lat[(size_t)m * D + j] = w->W[0][(size_t)m * (3 + D) + 3 + j];
+      b0[m] = w->b[0][m];
     }
-    for (int l = 0; l < nh; ++l)
+    for (int l = 0; l < L - 1; ++l)
       for (int m = 0; m < H; ++m) hbias[(size_t)l * H + m] = w->b[l + 1][m];
     for (int m = 0; m < H; ++m) wout[m] = w->W[L][m];
     bout = w->b[L][0];
-    if (e->cfg.precision == MPPI_PREC_FP32) {
-      hf32.resize((size_t)nh * H * H);
-      for (int l = 0; l < nh; ++l) {
+    if (e->cfg.precision == MPPI_PREC_FP32 && !e->fused) {
+      // 16x16x4 FP32 operand fragments: [mb][ks][lane] = W[16 mb + lane % 16][4 ks + lane / 16]
+      hf32.resize((size_t)(L - 1) * H * H);
+      for (int l = 0; l < L - 1; ++l) {
         const float* W = w->W[l + 1];
         float* P = &hf32[(size_t)l * H * H];
         for (int mb = 0; mb < H / 16; ++mb)
           for (int ks = 0; ks < H / 4; ++ks)
             for (int lane = 0; lane < 64; ++lane)
-              P[((size_t)mb * (H / 4) + ks) * 64 + lane] =
-                  W[(size_t)(16 * mb + lane % 16) * H + 4 * ks + lane / 16];
+              P[((size_t)mb * (H / 4) + ks) * 64 + lane] = W[(size_t)(16 * mb + lane % 16) * H + 4 * ks + lane / 16];
       }
-    } else {
+    }
+    if (e->fused) {
       int rc = pack_lowp_weights(e->cfg.precision, H, L, w, hlp, wsc, asc, ainv);
       if (rc != MPPI_OK) return rc;
     }
   }
-  // one device allocation for all of it
   const uint64_t o_w1p = 0;
   const uint64_t o_hb = align_up(o_w1p + 4 * w1p.size());
   const uint64_t o_wo = align_up(o_hb + 4 * hbias.size());
-  const uint64_t o_hf = align_up(o_wo + 4 * wout.size());
+  const uint64_t o_w0 = align_up(o_wo + 4 * wout.size());
+  const uint64_t o_b0 = align_up(o_w0 + 8 * w0lat.size());
+  const uint64_t o_hf = align_up(o_b0 + 8 * b0.size());
   const uint64_t o_lp = align_up(o_hf + 4 * hf32.size());
   const uint64_t o_ws = align_up(o_lp + hlp.size());
   const uint64_t o_as = align_up(o_ws + 4 * wsc.size());
@@ -523,6 +664,8 @@ int upload_weights(mppi_engine* e, const mppi_sdf_weights* w) {
   HIPCHK(e, hipMemcpy(b + o_w1p, w1p.data(), 4 * w1p.size(), hipMemcpyHostToDevice));
   HIPCHK(e, hipMemcpy(b + o_hb, hbias.data(), 4 * hbias.size(), hipMemcpyHostToDevice));
   HIPCHK(e, hipMemcpy(b + o_wo, wout.data(), 4 * wout.size(), hipMemcpyHostToDevice));
+  HIPCHK(e, hipMemcpy(b + o_w0, w0lat.data(), 8 * w0lat.size(), hipMemcpyHostToDevice));
+  HIPCHK(e, hipMemcpy(b + o_b0, b0.data(), 8 * b0.size(), hipMemcpyHostToDevice));
   if (!hf32.empty()) HIPCHK(e, hipMemcpy(b + o_hf, hf32.data(), 4 * hf32.size(), hipMemcpyHostToDevice));
   if (!hlp.empty()) HIPCHK(e, hipMemcpy(b + o_lp, hlp.data(), hlp.size(), hipMemcpyHostToDevice));
   HIPCHK(e, hipMemcpy(b + o_ws, wsc.data(), 4 * wsc.size(), hipMemcpyHostToDevice));
@@ -535,6 +678,8 @@ int upload_weights(mppi_engine* e, const mppi_sdf_weights* w) {
   dw.w1p = (const float*)(b + o_w1p);
   dw.hbias = (const float*)(b + o_hb);
   dw.wout = (const float*)(b + o_wo);
+  dw.w0lat = (const double*)(b + o_w0);
+  dw.b0 = (const double*)(b + o_b0);
   dw.bout = bout;
   dw.hidden_f32 = hf32.empty() ? nullptr : (const float*)(b + o_hf);
   dw.hidden_lp = hlp.empty() ? nullptr : (const void*)(b + o_lp);
@@ -544,15 +689,9 @@ int upload_weights(mppi_engine* e, const mppi_sdf_weights* w) {
   return MPPI_OK;
 }
 
-// ---------------------------------------------------------------- served path
 void scheduler_loop(mppi_engine* e);
 
 }  // namespace
-
-// Prepare and launch one batch of admitted requests on stream index si.
-// Caller holds e->mu.  Returns a status; on failure nothing is launched.
-static int launch_batch(mppi_engine* e, std::vector<std::pair<uint64_t, OwnedRequest*>>& items,
-                        int si, Batch& out);
 
 extern "C" {
 
@@ -562,7 +701,7 @@ const char* mppi_status_str(int s) {
     case MPPI_PENDING: return "pending";
     case MPPI_EINVAL: return "invalid argument";
     case MPPI_ENOMEM: return "out of device memory or over the budget";
-    case MPPI_EAGAIN: return "queue full or no free instance slot, retry";
+    case MPPI_EAGAIN: return "queue full, instance busy or no free instance slot: retry";
     case MPPI_ENOTFOUND: return "unknown or retired ticket";
     case MPPI_ENUMERIC: return "every rollout cost is non-finite";
     case MPPI_EDEVICE: return "HIP device error";
@@ -573,8 +712,7 @@ const char* mppi_status_str(int s) {
 int mppi_create(const mppi_config* cfg, const mppi_sdf_weights* w, mppi_engine** out) {
   if (!cfg || !out) return MPPI_EINVAL;
   const mppi_config& c = *cfg;
-  if (c.precision < 0 || c.precision > 3 || c.path < 0 || c.path > 1 || c.sdf_kind < 0 ||
-      c.sdf_kind > 1)
+  if (c.precision < 0 || c.precision > 3 || c.path < 0 || c.path > 1 || c.sdf_kind < 0 || c.sdf_kind > 1)
     return MPPI_EINVAL;
   if (c.latent_dim != kLatent) return MPPI_EINVAL;
   if (c.sdf_kind == MPPI_SDF_MLP) {
@@ -586,16 +724,16 @@ int mppi_create(const mppi_config* cfg, const mppi_sdf_weights* w, mppi_engine**
     if (c.precision == MPPI_PREC_FP8 && !w->act_scale) return MPPI_EINVAL;
   }
   if (c.path == MPPI_PATH_PLAIN && c.precision != MPPI_PREC_FP32) return MPPI_EINVAL;
-  if (c.K_max < 1 || c.K_max > kMaxK || c.T_max < 1 || c.T_max > kMaxT || c.G_max < 1 ||
-      c.G_max > kMaxG)
+  if (c.K_max < 1 || c.K_max > kMaxK || c.T_max < 1 || c.T_max > kMaxT || c.G_max < 1 || c.G_max > kMaxG)
     return MPPI_EINVAL;
   if (c.max_instances < 1 || c.max_inflight < 1 || c.queue_depth < 1) return MPPI_EINVAL;
   if (!(c.mass > 0.0) || !isfin(c.mass) || !isfin(c.gravity)) return MPPI_EINVAL;
   for (int i = 0; i < 4; ++i)
     if (!isfin(c.u_lo[i]) || !isfin(c.u_hi[i]) || c.u_lo[i] > c.u_hi[i]) return MPPI_EINVAL;
+  if (!c.device_pool && c.hbm_budget_bytes == 0) return MPPI_EINVAL;
 
   int ndev = 0;
-  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= c.device || c.device < 0) return MPPI_EDEVICE;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || c.device < 0 || ndev <= c.device) return MPPI_EDEVICE;
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, c.device) != hipSuccess) return MPPI_EDEVICE;
   if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) return MPPI_EDEVICE;
@@ -604,55 +742,54 @@ int mppi_create(const mppi_config* cfg, const mppi_sdf_weights* w, mppi_engine**
   auto e = std::make_unique<mppi_engine>();
   e->cfg = c;
   e->dev = c.device;
+  e->fused = c.path == MPPI_PATH_FUSED;
   e->H = c.sdf_kind == MPPI_SDF_MLP ? c.hidden : 64;
   e->L = c.sdf_kind == MPPI_SDF_MLP ? c.n_hidden : 2;
-  // streams
+  auto bail = [&](int rc) {
+    for (size_t i = 0; i < e->streams.size(); ++i)
+      if (i > 0 || e->own_stream0) hipStreamDestroy(e->streams[i]);
+    for (auto& ev : e->ev)
+      if (ev) hipEventDestroy(ev);
+    if (e->own_pool && e->pool) hipFree(e->pool);
+    if (e->wmem) hipFree(e->wmem);
+    if (e->instU) hipFree(e->instU);
+    if (e->instTick) hipFree(e->instTick);
+    return rc;
+  };
   hipStream_t s0 = (hipStream_t)c.stream;
   if (!s0) {
-    if (hipStreamCreateWithFlags(&s0, hipStreamNonBlocking) != hipSuccess) return MPPI_EDEVICE;
+    if (hipStreamCreateWithFlags(&s0, hipStreamNonBlocking) != hipSuccess) return bail(MPPI_EDEVICE);
     e->own_stream0 = true;
   }
   e->streams.push_back(s0);
   for (int i = 0; i < 3; ++i) {
     hipStream_t s;
-    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return MPPI_EDEVICE;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return bail(MPPI_EDEVICE);
     e->streams.push_back(s);
   }
   for (auto& ev : e->ev)
-    if (hipEventCreate(&ev) != hipSuccess) return MPPI_EDEVICE;
-  // weights
+    if (hipEventCreate(&ev) != hipSuccess) return bail(MPPI_EDEVICE);
   int rc = upload_weights(e.get(), w);
-  if (rc != MPPI_OK) return rc;
-  // device pool for per-solve blocks
+  if (rc != MPPI_OK) return bail(rc);
   if (c.device_pool) {
     e->pool = (char*)c.device_pool;
     e->pool_bytes = c.device_pool_bytes;
   } else {
     e->pool_bytes = c.hbm_budget_bytes;
-    if (e->pool_bytes == 0) return MPPI_EINVAL;
-    if (hipMalloc(&e->pool, e->pool_bytes) != hipSuccess) return MPPI_ENOMEM;
+    if (hipMalloc(&e->pool, e->pool_bytes) != hipSuccess) return bail(MPPI_ENOMEM);
     e->own_pool = true;
   }
   e->arena.reset(e->pool_bytes);
-  // instance table
   const size_t nI = (size_t)c.max_instances;
-  if (hipMalloc(&e->instU, sizeof(double) * 4 * c.T_max * nI) != hipSuccess) return MPPI_ENOMEM;
-  if (hipMalloc(&e->instTick, sizeof(uint32_t) * nI) != hipSuccess) return MPPI_ENOMEM;
-  if (hipMemset(e->instTick, 0, sizeof(uint32_t) * nI) != hipSuccess) return MPPI_EDEVICE;
-  if (hipHostMalloc((void**)&e->hover_pinned, sizeof(double) * 4 * c.T_max, hipHostMallocDefault) !=
-      hipSuccess)
-    return MPPI_ENOMEM;
-  for (int t = 0; t < c.T_max; ++t) {
-    e->hover_pinned[4 * t] = c.mass * c.gravity;
-    e->hover_pinned[4 * t + 1] = e->hover_pinned[4 * t + 2] = e->hover_pinned[4 * t + 3] = 0.0;
-  }
-  // pinned staging for the blocking path
-  e->stage_bytes = solve_layout(1, c.T_max, c.G_max, e->H, false, 0).upload_bytes;
-  if (hipHostMalloc((void**)&e->stage, e->stage_bytes, hipHostMallocDefault) != hipSuccess)
-    return MPPI_ENOMEM;
-  e->stats.budget = c.hbm_budget_bytes ? c.hbm_budget_bytes : e->pool_bytes;
-  e->adm = std::make_unique<Admission>(e->stats.budget, c.max_inflight, c.queue_depth);
-  if (hipDeviceSynchronize() != hipSuccess) return MPPI_EDEVICE;
+  if (hipMalloc(&e->instU, sizeof(double) * 4 * c.T_max * nI) != hipSuccess) return bail(MPPI_ENOMEM);
+  if (hipMalloc(&e->instTick, sizeof(uint32_t) * nI) != hipSuccess) return bail(MPPI_ENOMEM);
+  if (hipMemset(e->instTick, 0, sizeof(uint32_t) * nI) != hipSuccess) return bail(MPPI_EDEVICE);
+  e->hover.assign((size_t)4 * c.T_max, 0.0);
+  for (int t = 0; t < c.T_max; ++t) e->hover[4 * t] = c.mass * c.gravity;
+  const uint64_t budget = c.hbm_budget_bytes ? std::min<uint64_t>(c.hbm_budget_bytes, e->pool_bytes) : e->pool_bytes;
+  e->stats.budget = budget;
+  e->adm = std::make_unique<Admission>(budget, c.max_inflight, c.queue_depth);
+  if (hipDeviceSynchronize() != hipSuccess) return bail(MPPI_EDEVICE);
   mppi_engine* raw = e.release();
   raw->sched = std::thread(scheduler_loop, raw);
   *out = raw;
@@ -669,8 +806,6 @@ int mppi_destroy(mppi_engine* e) {
   if (e->sched.joinable()) e->sched.join();
   hipSetDevice(e->dev);
   for (auto& s : e->streams) hipStreamSynchronize(s);
-  for (auto& b : e->inflight)
-    if (b.done) hipEventDestroy(b.done);
   for (auto& ev : e->ev)
     if (ev) hipEventDestroy(ev);
   for (size_t i = 0; i < e->streams.size(); ++i)
@@ -679,8 +814,6 @@ int mppi_destroy(mppi_engine* e) {
   if (e->wmem) hipFree(e->wmem);
   if (e->instU) hipFree(e->instU);
   if (e->instTick) hipFree(e->instTick);
-  if (e->hover_pinned) hipHostFree(e->hover_pinned);
-  if (e->stage) hipHostFree(e->stage);
   delete e;
   return MPPI_OK;
 }
@@ -690,87 +823,35 @@ int mppi_step(mppi_engine* e, const mppi_request* r, mppi_result* out) {
   if (e->sticky.load()) return MPPI_EDEVICE;
   std::lock_guard<std::mutex> lk(e->mu);
   hipSetDevice(e->dev);
-  double Lo[16];
-  int rc = validate(e, r, Lo);
+  const uint64_t t_submit = now_ns();
+  Staged sg;
+  const bool exports = out->samples || out->positions || out->sdf;
+  int rc = stage(e, {r}, out->weights != nullptr, out->costs != nullptr, exports, sg);
   if (rc != MPPI_OK) return rc;
-  auto s = std::make_unique<Solve>();
-  s->t_submit = now_ns();
-  s->K = r->K;
-  s->T = r->T;
-  s->G = r->G;
-  s->flags = r->flags;
-  s->want_w = out->weights != nullptr;
-  s->want_J = out->costs != nullptr;
-  const bool fused = e->cfg.path == MPPI_PATH_FUSED;
-  s->exports = !fused && (out->samples || out->positions || out->sdf);
-  rc = acquire_slot(e, r->instance_id, &s->slot);
-  if (rc != MPPI_OK) return rc;
-  if (e->inst[s->slot].busy) return MPPI_EAGAIN;  // a served solve of this instance is pending
-  if (fused) {
-    // a one-solve batch through the served machinery, waited on here
-    std::vector<std::pair<uint64_t, OwnedRequest*>> items;
-    OwnedRequest own;
-    own.take(*r, e->cfg.latent_dim);
-    items.push_back({0, &own});
-    Batch b;
-    rc = launch_batch(e, items, 0, b);
-    if (rc != MPPI_OK) return rc;
-    HIPCHK(e, hipEventSynchronize(b.done));
-    Solve* bs = b.solves[0].get();
-    bs->t_done = now_ns();
-    bs->t_submit = s->t_submit;
-    bs->t_admit = s->t_submit;
-    bs->want_w = s->want_w;
-    fill_result(e, bs, out);
-    retire_instance(e, bs);
-    e->arena.release(bs->off, bs->bytes);
-    if (b.aux_bytes) e->arena.release(b.aux_off, b.aux_bytes);
-    hipEventDestroy(b.done);
-    e->stats.completed++;
-    return out->status;
-  }
-  s->lay = solve_layout(r->K, r->T, r->G, e->H, false, 0);
-  s->bytes = s->lay.total;
-  if (!e->arena.alloc(s->bytes, &s->off)) return MPPI_ENOMEM;
-  char* base = e->pool + s->off;
-  pack_solve(e, r, s.get(), Lo, base, e->stage, false, 1);
   hipStream_t st = e->streams[0];
   const bool timing = e->cfg.flags & MPPI_CFG_TIMING;
-  auto fail = [&](hipError_t err) {
-    e->arena.release(s->off, s->bytes);
-    return dev_fail(e, err);
-  };
-  hipError_t err = hipMemcpyAsync(base, e->stage, s->lay.upload_bytes, hipMemcpyHostToDevice, st);
-  if (err != hipSuccess) return fail(err);
   if (timing) hipEventRecord(e->ev[2], st);
-  PlainShape shp{r->K, r->T, r->G, e->cfg.sdf_kind};
-  err = launch_plain((const SolveDesc*)(base + s->lay.desc), shp, e->dw, st,
-                     timing ? e->ev[0] : nullptr, timing ? e->ev[1] : nullptr);
-  if (err != hipSuccess) return fail(err);
-  if (timing) hipEventRecord(e->ev[3], st);
-  rc = enqueue_fetch(e, s.get(), st);
+  rc = launch_staged(e, sg, st, timing ? e->ev[0] : nullptr, timing ? e->ev[1] : nullptr);
+  if (rc == MPPI_OK && timing) hipEventRecord(e->ev[3], st);
+  Solve* s = sg.solves[0].get();
+  if (rc == MPPI_OK) rc = enqueue_fetch(e, s, st);
+  if (rc == MPPI_OK) {
+    hipError_t err = hipStreamSynchronize(st);
+    if (err != hipSuccess) rc = dev_fail(e, err);
+  }
   if (rc != MPPI_OK) {
-    e->arena.release(s->off, s->bytes);
+    release_staged(e, sg, true);
     return rc;
   }
-  err = hipStreamSynchronize(st);
-  if (err != hipSuccess) return fail(err);
-  s->t_admit = s->t_submit;
+  s->t_submit = s->t_admit = t_submit;
   s->t_done = now_ns();
   if (timing) {
-    float ms = 0.0f;
-    if (hipEventElapsedTime(&ms, e->ev[0], e->ev[1]) == hipSuccess) {
-      e->stats.sdf_ms += ms;
-      e->stats.sdf_launches++;
-    }
-    if (hipEventElapsedTime(&ms, e->ev[2], e->ev[3]) == hipSuccess) {
-      e->stats.solve_ms += ms;
-      e->stats.solve_launches++;
-    }
+    add_time(e, e->ev[0], e->ev[1], true);
+    add_time(e, e->ev[2], e->ev[3], false);
   }
-  fill_result(e, s.get(), out);
-  retire_instance(e, s.get());
-  e->arena.release(s->off, s->bytes);
+  fill_result(s, out);
+  note_result(e, s);
+  release_staged(e, sg, true);
   e->stats.completed++;
   e->stats.bytes_peak = std::max<uint64_t>(e->stats.bytes_peak, e->arena.peak());
   return out->status;
@@ -783,8 +864,7 @@ int mppi_submit(mppi_engine* e, const mppi_request* r, uint64_t* ticket) {
   std::lock_guard<std::mutex> lk(e->mu);
   int rc = validate(e, r, Lo);
   if (rc != MPPI_OK) return rc;
-  const bool fused = e->cfg.path == MPPI_PATH_FUSED;
-  const uint64_t fp = footprint_of(e, r->K, r->T, r->G, fused);
+  const uint64_t fp = layout_for(e, r->K, r->T, r->G).total;
   const uint64_t t = e->next_ticket;
   rc = e->adm->push(AdmissionItem{t, r->instance_id, fp});
   if (rc == -2) return MPPI_ENOMEM;
@@ -806,9 +886,9 @@ int mppi_poll(mppi_engine* e, uint64_t ticket, mppi_result* out) {
     if (e->ticket_submit_ns.count(ticket)) return e->sticky.load() ? MPPI_EDEVICE : MPPI_PENDING;
     return MPPI_ENOTFOUND;
   }
-  Solve* s = it->second.get();
   if (!out->U_star) return MPPI_EINVAL;
-  fill_result(e, s, out);
+  const Solve* s = it->second.get();
+  fill_result(s, out);
   const int st = out->status;
   e->done.erase(it);
   e->ticket_submit_ns.erase(ticket);
@@ -818,9 +898,7 @@ int mppi_poll(mppi_engine* e, uint64_t ticket, mppi_result* out) {
 int mppi_drain(mppi_engine* e) {
   if (!e) return MPPI_EINVAL;
   std::unique_lock<std::mutex> lk(e->mu);
-  e->cv.wait(lk, [&] {
-    return e->sticky.load() != 0 || (e->adm->queued() == 0 && e->inflight.empty());
-  });
+  e->cv.wait(lk, [&] { return e->sticky.load() != 0 || (e->adm->queued() == 0 && e->inflight.empty()); });
   return e->sticky.load() ? MPPI_EDEVICE : MPPI_OK;
 }
 
@@ -843,187 +921,138 @@ void mppi_reset_stats(mppi_engine* e) {
 
 uint64_t mppi_solve_footprint(const mppi_engine* e, int32_t K, int32_t T, int32_t G) {
   if (!e || K < 1 || T < 1 || G < 1) return 0;
-  return footprint_of(e, K, T, G, e->cfg.path == MPPI_PATH_FUSED);
+  return layout_for(e, K, T, G).total;
+}
+
+int mppi_batch_create(mppi_engine* e, const mppi_request* reqs, int32_t n, mppi_batch** out) {
+  if (!e || !reqs || n < 1 || !out) return MPPI_EINVAL;
+  if (e->sticky.load()) return MPPI_EDEVICE;
+  std::lock_guard<std::mutex> lk(e->mu);
+  hipSetDevice(e->dev);
+  auto b = std::make_unique<mppi_batch>();
+  std::vector<const mppi_request*> rs;
+  for (int i = 0; i < n; ++i) rs.push_back(&reqs[i]);
+  int rc = stage(e, rs, true, true, false, b->st);
+  if (rc != MPPI_OK) return rc;
+  for (hipEvent_t* ev : {&b->t0, &b->t1, &b->s0, &b->s1})
+    if (hipEventCreate(ev) != hipSuccess) {
+      release_staged(e, b->st, true);
+      for (hipEvent_t x : {b->t0, b->t1, b->s0, b->s1})
+        if (x) hipEventDestroy(x);
+      return dev_fail(e, hipErrorOutOfMemory);
+    }
+  *out = b.release();
+  return MPPI_OK;
+}
+
+int mppi_batch_run(mppi_engine* e, mppi_batch* b) {
+  if (!e || !b) return MPPI_EINVAL;
+  if (e->sticky.load()) return MPPI_EDEVICE;
+  std::lock_guard<std::mutex> lk(e->mu);
+  hipStream_t st = e->streams[0];
+  const bool timing = e->cfg.flags & MPPI_CFG_TIMING;
+  if (timing && b->launched) {
+    // fold the previous launch's times in before its events are reused
+    const hipError_t err = hipEventSynchronize(b->s1);
+    if (err != hipSuccess) return dev_fail(e, err);
+    add_time(e, b->t0, b->t1, true);
+    add_time(e, b->s0, b->s1, false);
+    b->launched = false;
+  }
+  if (timing) hipEventRecord(b->s0, st);
+  int rc = launch_staged(e, b->st, st, timing ? b->t0 : nullptr, timing ? b->t1 : nullptr);
+  if (rc != MPPI_OK) return rc;
+  if (timing) {
+    hipEventRecord(b->s1, st);
+    b->launched = true;
+  }
+  return MPPI_OK;
+}
+
+int mppi_batch_wait(mppi_engine* e, mppi_batch* b) {
+  if (!e || !b) return MPPI_EINVAL;
+  std::lock_guard<std::mutex> lk(e->mu);
+  const hipError_t err = hipStreamSynchronize(e->streams[0]);
+  if (err != hipSuccess) return dev_fail(e, err);
+  if (b->launched) {
+    add_time(e, b->t0, b->t1, true);
+    add_time(e, b->s0, b->s1, false);
+    b->launched = false;
+  }
+  return MPPI_OK;
+}
+
+int mppi_batch_results(mppi_engine* e, mppi_batch* b, mppi_result* results) {
+  if (!e || !b || !results) return MPPI_EINVAL;
+  std::lock_guard<std::mutex> lk(e->mu);
+  hipStream_t st = e->streams[0];
+  for (auto& s : b->st.solves) {
+    int rc = enqueue_fetch(e, s.get(), st);
+    if (rc != MPPI_OK) return rc;
+  }
+  const hipError_t err = hipStreamSynchronize(st);
+  if (err != hipSuccess) return dev_fail(e, err);
+  const uint64_t t = now_ns();
+  for (size_t i = 0; i < b->st.solves.size(); ++i) {
+    Solve* s = b->st.solves[i].get();
+    s->t_submit = s->t_admit = s->t_done = t;
+    note_result(e, s);
+    fill_result(s, &results[i]);
+  }
+  return MPPI_OK;
+}
+
+int mppi_batch_destroy(mppi_engine* e, mppi_batch* b) {
+  if (!e || !b) return MPPI_EINVAL;
+  std::lock_guard<std::mutex> lk(e->mu);
+  hipStreamSynchronize(e->streams[0]);
+  release_staged(e, b->st, true);
+  for (hipEvent_t ev : {b->t0, b->t1, b->s0, b->s1})
+    if (ev) hipEventDestroy(ev);
+  delete b;
+  return MPPI_OK;
 }
 
 }  // extern "C"
 
-// ---------------------------------------------------------------- batches
-static int launch_batch(mppi_engine* e, std::vector<std::pair<uint64_t, OwnedRequest*>>& items,
-                        int si, Batch& out) {
-  const bool fused = e->cfg.path == MPPI_PATH_FUSED;
-  hipStream_t st = e->streams[si];
-  out.stream_idx = si;
-  std::vector<std::unique_ptr<Solve>> solves;
-  std::vector<char> host;
-  auto release_all = [&]() {
-    for (auto& s : solves) e->arena.release(s->off, s->bytes);
-    if (out.aux_bytes) e->arena.release(out.aux_off, out.aux_bytes);
-    out.aux_bytes = 0;
-  };
-  int total_tiles = 0;
-  std::vector<int2> tiles;
-  for (auto& it : items) {
-    const mppi_request* r = &it.second->req;
-    double Lo[16];
-    int rc = validate(e, r, Lo);
-    auto s = std::make_unique<Solve>();
-    s->ticket = it.first;
-    s->K = r->K;
-    s->T = r->T;
-    s->G = r->G;
-    s->flags = r->flags;
-    s->want_w = true;
-    s->want_J = true;
-    if (rc == MPPI_OK) rc = acquire_slot(e, r->instance_id, &s->slot);
-    if (rc != MPPI_OK) {
-      release_all();
-      return rc;
-    }
-    const int R = fused ? fused_tile_rollouts(e->cfg.precision, e->H, r->G) : 1;
-    const int nt = fused ? (r->K + R - 1) / R : 0;
-    s->lay = solve_layout(r->K, r->T, r->G, e->H, fused, nt);
-    s->bytes = s->lay.total;
-    if (!e->arena.alloc(s->bytes, &s->off)) {
-      release_all();
-      return MPPI_ENOMEM;
-    }
-    host.assign(s->lay.upload_bytes, 0);
-    char* base = e->pool + s->off;
-    pack_solve(e, r, s.get(), Lo, base, host.data(), fused, R);
-    // The copy is synchronous from pageable memory into the device block
-    // before any kernel of this batch is enqueued.
-    hipError_t err = hipMemcpyAsync(base, host.data(), s->lay.upload_bytes, hipMemcpyHostToDevice, st);
-    if (err == hipSuccess) err = hipStreamSynchronize(st);
-    if (err != hipSuccess) {
-      release_all();
-      return dev_fail(e, err);
-    }
-    if (fused) {
-      for (int i = 0; i < nt; ++i) tiles.push_back(int2{(int)solves.size(), i * R});
-      total_tiles += nt;
-    }
-    e->inst[s->slot].busy = true;
-    solves.push_back(std::move(s));
-  }
-  const bool timing = e->cfg.flags & MPPI_CFG_TIMING;
-  hipEvent_t t0 = nullptr, t1 = nullptr;
-  if (timing) {
-    hipEventCreate(&t0);
-    hipEventCreate(&t1);
-  }
-  if (!fused) {
-    for (auto& s : solves) {
-      PlainShape shp{s->K, s->T, s->G, e->cfg.sdf_kind};
-      hipError_t err = launch_plain((const SolveDesc*)(e->pool + s->off + s->lay.desc), shp, e->dw,
-                                    st, timing ? t0 : nullptr, timing ? t1 : nullptr);
-      if (err != hipSuccess) {
-        release_all();
-        return dev_fail(e, err);
-      }
-    }
-  } else {
-    // descriptor array + tile list + work counter in one aux block
-    const size_t nS = solves.size();
-    out.aux_bytes = align_up(sizeof(SolveDesc) * nS) + align_up(sizeof(int2) * tiles.size()) + 256;
-    if (!e->arena.alloc(out.aux_bytes, &out.aux_off)) {
-      out.aux_bytes = 0;
-      release_all();
-      return MPPI_ENOMEM;
-    }
-    // longest tiles first (work per tile grows with T and G)
-    std::stable_sort(tiles.begin(), tiles.end(), [&](const int2& a, const int2& b) {
-      const Solve* sa = solves[a.x].get();
-      const Solve* sb = solves[b.x].get();
-      return sa->T * sa->G > sb->T * sb->G;
-    });
-    std::vector<char> aux(out.aux_bytes, 0);
-    for (size_t i = 0; i < nS; ++i) memcpy(aux.data() + i * sizeof(SolveDesc), &solves[i]->desc, sizeof(SolveDesc));
-    const uint64_t o_tiles = align_up(sizeof(SolveDesc) * nS);
-    memcpy(aux.data() + o_tiles, tiles.data(), sizeof(int2) * tiles.size());
-    const uint64_t o_cnt = o_tiles + align_up(sizeof(int2) * tiles.size());
-    char* ab = e->pool + out.aux_off;
-    hipError_t err = hipMemcpyAsync(ab, aux.data(), out.aux_bytes, hipMemcpyHostToDevice, st);
-    if (err == hipSuccess) err = hipStreamSynchronize(st);
-    if (err != hipSuccess) {
-      release_all();
-      return dev_fail(e, err);
-    }
-    int maxT = 1;
-    for (auto& s : solves) maxT = std::max(maxT, s->T);
-    FusedBatch fb{(const SolveDesc*)ab, (const int2*)(ab + o_tiles), (int)tiles.size(),
-                  (uint32_t*)(ab + o_cnt)};
-    err = launch_fused(fb, e->dw, maxT, st, timing ? t0 : nullptr, timing ? t1 : nullptr);
-    if (err != hipSuccess) {
-      release_all();
-      return dev_fail(e, err);
-    }
-  }
-  for (auto& s : solves) {
-    int rc = enqueue_fetch(e, s.get(), st);
-    if (rc != MPPI_OK) {
-      release_all();
-      return rc;
-    }
-  }
-  hipError_t err = hipEventCreateWithFlags(&out.done, hipEventDisableTiming);
-  if (err == hipSuccess) err = hipEventRecord(out.done, st);
-  if (err != hipSuccess) {
-    release_all();
-    return dev_fail(e, err);
-  }
-  if (timing) {
-    hipEventSynchronize(t1);
-    float ms = 0.0f;
-    if (hipEventElapsedTime(&ms, t0, t1) == hipSuccess) {
-      e->stats.sdf_ms += ms;
-      e->stats.sdf_launches++;
-    }
-    hipEventDestroy(t0);
-    hipEventDestroy(t1);
-  }
-  e->stats.waves++;
-  out.solves = std::move(solves);
-  (void)total_tiles;
-  return MPPI_OK;
-}
-
 namespace {
 
-// Served path: admit, batch, launch, complete.  One batch per free stream;
-// requests that arrive while batches run are admitted into the next batch.
+// Served path.  Each pass: retire finished batches (their budget, instances
+// and results are released), then admit whatever fits and launch it as one
+// batch on a free serving stream.  Requests arriving while batches run are
+// admitted into the next batch as memory and streams free up.
 void scheduler_loop(mppi_engine* e) {
   hipSetDevice(e->dev);
-  const int nstreams = (int)e->streams.size() - 1;   // streams 1.. for serving
+  const int nstreams = (int)e->streams.size() - 1;
+  const bool timing = e->cfg.flags & MPPI_CFG_TIMING;
   std::unique_lock<std::mutex> lk(e->mu);
   while (true) {
-    // 1. retire finished batches
     for (size_t i = 0; i < e->inflight.size();) {
-      Batch& b = e->inflight[i];
-      hipError_t q = hipEventQuery(b.done);
+      Inflight& b = e->inflight[i];
+      const hipError_t q = hipEventQuery(b.done);
       if (q == hipErrorNotReady) {
         ++i;
         continue;
       }
       if (q != hipSuccess) e->sticky.store(MPPI_EDEVICE);
+      if (timing) add_time(e, b.t0, b.t1, true);
       const uint64_t tnow = now_ns();
-      for (auto& s : b.solves) {
+      for (auto& s : b.st.solves) {
         s->t_done = tnow;
-        retire_instance(e, s.get());
-        e->arena.release(s->off, s->bytes);
+        note_result(e, s.get());
         e->adm->complete(s->footprint);
         const int st = s->res.empty() ? MPPI_EDEVICE : (int)s->res[4 * s->T + RES_STATUS];
         if (st != MPPI_OK) e->stats.failed++;
         e->stats.completed++;
-        e->done[s->ticket] = std::move(s);
       }
-      if (b.aux_bytes) e->arena.release(b.aux_off, b.aux_bytes);
-      hipEventDestroy(b.done);
+      release_staged(e, b.st, true);
+      for (auto& s : b.st.solves) e->done[s->ticket] = std::move(s);
+      for (hipEvent_t ev : {b.done, b.t0, b.t1})
+        if (ev) hipEventDestroy(ev);
       e->inflight.erase(e->inflight.begin() + i);
       e->cv.notify_all();
     }
     if (e->stop && e->inflight.empty()) break;
-    // 2. admit and launch while a serving stream is free
     bool launched = false;
     if (!e->stop && !e->sticky.load() && (int)e->inflight.size() < nstreams) {
       auto adm = e->adm->admit([&](uint64_t id) {
@@ -1035,28 +1064,48 @@ void scheduler_loop(mppi_engine* e) {
         for (auto& b : e->inflight) used[b.stream_idx] = true;
         int si = 1;
         while (si <= nstreams && used[si]) ++si;
-        std::vector<std::pair<uint64_t, OwnedRequest*>> items;
-        for (auto& a : adm) items.push_back({a.ticket, &e->pending[a.ticket]});
-        Batch b;
+        std::vector<const mppi_request*> rs;
+        for (auto& a : adm) rs.push_back(&e->pending[a.ticket].req);
+        Inflight b;
+        b.stream_idx = si;
         const uint64_t tadm = now_ns();
-        int rc = launch_batch(e, items, si, b);
+        int rc = stage(e, rs, true, true, false, b.st);
+        hipStream_t st = e->streams[si];
+        if (rc == MPPI_OK && timing) {
+          hipEventCreate(&b.t0);
+          hipEventCreate(&b.t1);
+        }
+        if (rc == MPPI_OK) rc = launch_staged(e, b.st, st, b.t0, b.t1);
+        for (size_t i = 0; rc == MPPI_OK && i < b.st.solves.size(); ++i)
+          rc = enqueue_fetch(e, b.st.solves[i].get(), st);
+        if (rc == MPPI_OK && hipEventCreateWithFlags(&b.done, hipEventDisableTiming) != hipSuccess)
+          rc = dev_fail(e, hipErrorOutOfMemory);
+        if (rc == MPPI_OK && hipEventRecord(b.done, st) != hipSuccess) rc = dev_fail(e, hipErrorUnknown);
         if (rc == MPPI_OK) {
-          for (size_t i = 0; i < b.solves.size(); ++i) {
-            b.solves[i]->footprint = adm[i].footprint;
-            b.solves[i]->t_submit = e->ticket_submit_ns[adm[i].ticket];
-            b.solves[i]->t_admit = tadm;
+          for (size_t i = 0; i < b.st.solves.size(); ++i) {
+            b.st.solves[i]->ticket = adm[i].ticket;
+            b.st.solves[i]->footprint = adm[i].footprint;
+            b.st.solves[i]->t_submit = e->ticket_submit_ns[adm[i].ticket];
+            b.st.solves[i]->t_admit = tadm;
           }
           e->stats.admitted += adm.size();
+          e->stats.waves++;
           e->inflight.push_back(std::move(b));
           launched = true;
         } else {
-          // fail these requests with the status; their budget is returned
+          if (!b.st.solves.empty()) {
+            hipStreamSynchronize(st);
+            release_staged(e, b.st, true);
+          }
+          for (hipEvent_t ev : {b.done, b.t0, b.t1})
+            if (ev) hipEventDestroy(ev);
           for (auto& a : adm) {
             auto s = std::make_unique<Solve>();
             s->ticket = a.ticket;
             s->T = e->pending[a.ticket].req.T;
             s->res.assign(4 * s->T + RES_SCALARS, 0.0);
             s->res[4 * s->T + RES_STATUS] = rc;
+            s->want_w = s->want_J = false;
             s->t_submit = e->ticket_submit_ns[a.ticket];
             s->t_done = now_ns();
             e->adm->complete(a.footprint);
@@ -1070,7 +1119,6 @@ void scheduler_loop(mppi_engine* e) {
     }
     if (launched) continue;
     if (!e->inflight.empty()) {
-      // poll the running batches without holding the lock for long
       lk.unlock();
       std::this_thread::sleep_for(std::chrono::microseconds(20));
       lk.lock();

@@ -75,8 +75,8 @@ class Arena {
 
 // Byte layout of one solve's device block (descriptor, request data, buffers).
 struct SolveLayout {
-  uint64_t desc, U, Rt, base, cfold, los;            // request part (uploaded)
-  uint64_t samples, pos, sdf, Jpart, J, wt, wn, result, partials, tiles_done;
+  uint64_t desc, U, Rt, base, z, los;                // request part (uploaded)
+  uint64_t cfold, samples, pos, sdf, Jpart, J, wt, wn, result, partials, tiles_done;
   uint64_t upload_bytes, total;
 };
 
@@ -88,9 +88,10 @@ inline SolveLayout solve_layout(int K, int T, int G, int H, bool fused, int n_ti
   L.U = take(8ull * 4 * T);
   L.Rt = take(4ull * 9 * G);
   L.base = take(4ull * 3 * G * (T + 1));
-  L.cfold = take(4ull * G * H);
+  L.z = take(4ull * G * 64);
   L.los = take(4ull * 2 * T);
   L.upload_bytes = o;
+  L.cfold = take(4ull * G * H);
   L.result = take(8ull * (4 * T + 10));
   L.J = take(4ull * K);
   L.wn = take(8ull * K);

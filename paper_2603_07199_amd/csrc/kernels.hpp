@@ -22,6 +22,10 @@ struct PlainShape {
 hipError_t launch_plain(const SolveDesc* dd, const PlainShape& shape, const DeviceWeights& w,
                         hipStream_t s, hipEvent_t sdf_begin, hipEvent_t sdf_end);
 
+// Latent fold c_g = W1[:, 3:] z_g + b1 for the gates of n_solves descriptors.
+hipError_t launch_fold(const SolveDesc* descs, int n_solves, int G_max, const DeviceWeights& w,
+                       hipStream_t s);
+
 // Fused path: one persistent launch over the tiles of a batch of solves.
 struct FusedBatch {
   const SolveDesc* descs;    // device array of n_solves descriptors

@@ -24,6 +24,29 @@ __device__ __forceinline__ uint32_t solve_tick(const SolveDesc& d) {
   return d.tick_fixed == 0xFFFFFFFFu ? *d.tick_slot : d.tick_fixed;
 }
 
+// ------------------------------------------------------------------ latent fold
+// c_g = W1[:, 3:] z_g + b1 for every gate of every solve in descs (grid.y),
+// in FP64 and rounded once: the decoder's first layer applied to the latent
+// block of its input [p; z] (Section III-B), shared by all queries of a gate.
+__global__ __launch_bounds__(256) void k_fold(const SolveDesc* __restrict__ descs, DeviceWeights w) {
+  const SolveDesc& d = descs[blockIdx.y];
+  const int g = blockIdx.x;
+  if (g >= d.G || d.sdf_kind != 0) return;
+  const float* z = d.z + g * kLatent;
+  for (int m = threadIdx.x; m < d.H; m += blockDim.x) {
+    double acc = w.b0[m];
+    const double* wr = w.w0lat + (size_t)m * kLatent;
+    for (int j = 0; j < kLatent; ++j) acc = fma(wr[j], (double)z[j], acc);
+    d.cfold[g * d.H + m] = (float)acc;
+  }
+}
+
+hipError_t launch_fold(const SolveDesc* descs, int n_solves, int G_max, const DeviceWeights& w,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_fold, dim3(G_max, n_solves), dim3(256), 0, s, descs, w);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ rollout
 __global__ __launch_bounds__(256) void k_rollout(const SolveDesc* __restrict__ dd) {
   const SolveDesc& d = *dd;
@@ -341,8 +364,13 @@ static hipError_t launch_sdf_f32_h(const SolveDesc* dd, const DeviceWeights& w, 
 hipError_t launch_plain(const SolveDesc* dd, const PlainShape& sh, const DeviceWeights& w,
                         hipStream_t s, hipEvent_t sdf_begin, hipEvent_t sdf_end) {
   const int K = sh.K, T = sh.T;
+  hipError_t e = hipSuccess;
+  if (sh.sdf_kind == 0) {
+    e = launch_fold(dd, 1, sh.G, w, s);
+    if (e != hipSuccess) return e;
+  }
   hipLaunchKernelGGL(k_rollout, dim3((K + 255) / 256), dim3(256), 0, s, dd);
-  hipError_t e = hipGetLastError();
+  e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (sdf_begin) hipEventRecord(sdf_begin, s);
   const long npos = (long)K * T;

@@ -90,7 +90,8 @@ class mppi_stats(C.Structure):
 
 EXPORTED = ["mppi_create", "mppi_destroy", "mppi_step", "mppi_submit", "mppi_poll",
             "mppi_drain", "mppi_get_stats", "mppi_reset_stats", "mppi_status_str",
-            "mppi_solve_footprint"]
+            "mppi_solve_footprint", "mppi_batch_create", "mppi_batch_run", "mppi_batch_wait",
+            "mppi_batch_results", "mppi_batch_destroy"]
 
 _lib = None
 
@@ -117,8 +118,14 @@ def load_library(path=LIB_PATH):
     lib.mppi_status_str.restype = C.c_char_p
     lib.mppi_solve_footprint.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32]
     lib.mppi_solve_footprint.restype = C.c_uint64
+    lib.mppi_batch_create.argtypes = [C.c_void_p, P(mppi_request), C.c_int32, P(C.c_void_p)]
+    lib.mppi_batch_run.argtypes = [C.c_void_p, C.c_void_p]
+    lib.mppi_batch_wait.argtypes = [C.c_void_p, C.c_void_p]
+    lib.mppi_batch_results.argtypes = [C.c_void_p, C.c_void_p, P(mppi_result)]
+    lib.mppi_batch_destroy.argtypes = [C.c_void_p, C.c_void_p]
     for name in ("mppi_create", "mppi_destroy", "mppi_step", "mppi_submit", "mppi_poll",
-                 "mppi_drain", "mppi_get_stats"):
+                 "mppi_drain", "mppi_get_stats", "mppi_batch_create", "mppi_batch_run",
+                 "mppi_batch_wait", "mppi_batch_results", "mppi_batch_destroy"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -280,6 +287,50 @@ def mppi_drain(handle):
     return load_library().mppi_drain(handle)
 
 
+class Batch:
+    """Requests staged once in device memory (``mppi_batch_*``)."""
+
+    def __init__(self, handle, probs):
+        lib = load_library()
+        self.h = handle
+        self.probs = probs
+        self._reqs = [_Request(p) for p in probs]
+        arr = (mppi_request * len(probs))(*[r.req for r in self._reqs])
+        self._arr = arr
+        b = C.c_void_p()
+        rc = lib.mppi_batch_create(handle, arr, len(probs), C.byref(b))
+        if rc != MPPI_OK:
+            raise MPPIError(rc, "mppi_batch_create")
+        self.b = b
+
+    def run(self):
+        rc = load_library().mppi_batch_run(self.h, self.b)
+        if rc != MPPI_OK:
+            raise MPPIError(rc, "mppi_batch_run")
+
+    def wait(self):
+        rc = load_library().mppi_batch_wait(self.h, self.b)
+        if rc != MPPI_OK:
+            raise MPPIError(rc, "mppi_batch_wait")
+
+    def results(self):
+        rs = [_Result(p["K"], p["T"]) for p in self.probs]
+        arr = (mppi_result * len(rs))(*[r.res for r in rs])
+        rc = load_library().mppi_batch_results(self.h, self.b, arr)
+        if rc != MPPI_OK:
+            raise MPPIError(rc, "mppi_batch_results")
+        out = []
+        for r, raw in zip(rs, arr):
+            r.res = raw
+            out.append(r.as_dict())
+        return out
+
+    def close(self):
+        if self.b is not None:
+            load_library().mppi_batch_destroy(self.h, self.b)
+            self.b = None
+
+
 def default_config(model, K_max=8192, T_max=64, G_max=8, hidden=256, n_hidden=3,
                    precision="fp32", path="plain", sdf_kind="mlp", max_instances=4096,
                    max_inflight=64, queue_depth=4096, budget=1 << 30, seed=0, timing=False,
@@ -340,6 +391,9 @@ class Engine:
 
     def reset_stats(self):
         load_library().mppi_reset_stats(self.h)
+
+    def batch(self, probs):
+        return Batch(self.h, probs)
 
     def footprint(self, K, T, G):
         return int(load_library().mppi_solve_footprint(self.h, K, T, G))
