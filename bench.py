@@ -33,7 +33,7 @@ if ROOT not in sys.path:
 import scenarios as sc  # noqa: E402
 
 HBM_PEAK = 8.0e12
-PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "bf16x2": 2500.0, "fp8": 5000.0}
+PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "bf16x2": 2500.0, "bf16x3": 2500.0, "fp8": 5000.0}
 LAYERS = (67, 256, 256, 256, 1)
 K_, T_, G_ = 4096, 50, 4
 KERNEL_SOURCES = {"plain": "kernels_plain.hip", "fused": "kernels_fused.hip"}
@@ -128,10 +128,12 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--path", default="plain", choices=["plain", "fused"])
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "bf16x2", "fp8"])
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "bf16x2", "bf16x3", "fp8"])
     ap.add_argument("--batch", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="run one plain device copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -140,6 +142,14 @@ def main():
         sys.exit(2)
     from paper_2603_07199_amd import mppi as M
     M.load_library()
+    if args.copy_mib:
+        import torch
+        n = args.copy_mib << 20
+        src = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     main_leg = run_leg(M, args.path, args.precision, args.batch, args.steps, args.warmup)
     queries = args.batch * K_ * T_ * G_
@@ -158,7 +168,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp32": "f32", "bf16": "bf16", "bf16x2": "bf16x2", "fp8": "fp8"}[args.precision],
+        "dtype": {"fp32": "f32", "bf16": "bf16", "bf16x2": "bf16x2", "bf16x3": "bf16x3", "fp8": "fp8"}[args.precision],
         "data": "synthetic",
         "config": {"workload": f"MPPI solve K={K_} T={T_} dt=0.02 G={G_} decoder 67-256-256-256-1",
                    "path": args.path, "precision": args.precision, "solves_per_step": args.batch,

@@ -84,3 +84,15 @@ def mlp_fold(pg, z, W, b, contract="fp32", act_scales=None):
     c = _t(W[0])[:, 3:] @ _t(z) + _t(b[0])
     h = _softplus_t(_t(pg) @ _t(W[0])[:, :3].T + c)
     return _mlp_tail(h, W, b, contract, act_scales)[:, 0].numpy()
+
+
+def hidden_input_amax(pg, z, W, b):
+    """max |h_l| of every activation that feeds a hidden H x H layer (l = 1..L-1),
+    float64, over query points pg: the calibration statistic of the FP8
+    contract's static activation scales (scale = amax / 448)."""
+    h = _softplus_t(_t(pg) @ _t(W[0])[:, :3].T + (_t(W[0])[:, 3:] @ _t(z) + _t(b[0])))
+    out = []
+    for l in range(1, len(W) - 1):
+        out.append(float(torch.max(torch.abs(h))))
+        h = _softplus_t(h @ _t(W[l]).T + _t(b[l]))
+    return out

@@ -108,7 +108,7 @@ struct Aux {
   const SolveDesc* descs = nullptr;
   const int2* tiles = nullptr;
   uint32_t* counter = nullptr;
-  int n_tiles = 0, maxT = 1, maxG = 1;
+  int n_tiles = 0, maxT = 1, maxG = 1, maxTiles = 1;
 };
 
 struct Staged {
@@ -472,6 +472,7 @@ int stage(mppi_engine* e, const std::vector<const mppi_request*>& reqs, bool wan
       for (int t = 0; t < s->desc.n_tiles; ++t) tiles.push_back(int2{(int)i, t * R});
       a.maxT = std::max(a.maxT, s->T);
       a.maxG = std::max(a.maxG, s->G);
+      a.maxTiles = std::max(a.maxTiles, s->desc.n_tiles);
     }
     // longest tiles first (work per tile grows with T G); ties keep solve order
     std::stable_sort(tiles.begin(), tiles.end(), [&](const int2& x, const int2& y) {
@@ -523,7 +524,7 @@ int launch_staged(mppi_engine* e, Staged& sg, hipStream_t st, hipEvent_t t0, hip
   Aux& a = sg.aux;
   HIPCHK(e, launch_fold(a.descs, (int)sg.solves.size(), a.maxG, e->dw, st));
   FusedBatch fb{a.descs, a.tiles, a.n_tiles, a.counter};
-  HIPCHK(e, launch_fused(fb, e->dw, a.maxT, st, t0, t1));
+  HIPCHK(e, launch_fused(fb, (int)sg.solves.size(), e->dw, a.maxT, a.maxG, a.maxTiles, st, t0, t1));
   return MPPI_OK;
 }
 
@@ -712,7 +713,7 @@ const char* mppi_status_str(int s) {
 int mppi_create(const mppi_config* cfg, const mppi_sdf_weights* w, mppi_engine** out) {
   if (!cfg || !out) return MPPI_EINVAL;
   const mppi_config& c = *cfg;
-  if (c.precision < 0 || c.precision > 3 || c.path < 0 || c.path > 1 || c.sdf_kind < 0 || c.sdf_kind > 1)
+  if (c.precision < 0 || c.precision > 4 || c.path < 0 || c.path > 1 || c.sdf_kind < 0 || c.sdf_kind > 1)
     return MPPI_EINVAL;
   if (c.latent_dim != kLatent) return MPPI_EINVAL;
   if (c.sdf_kind == MPPI_SDF_MLP) {
@@ -723,7 +724,14 @@ int mppi_create(const mppi_config* cfg, const mppi_sdf_weights* w, mppi_engine**
       if (!w->W[l] || !w->b[l]) return MPPI_EINVAL;
     if (c.precision == MPPI_PREC_FP8 && !w->act_scale) return MPPI_EINVAL;
   }
+  if (c.precision == MPPI_PREC_BF16X3 && c.path != MPPI_PATH_FUSED) return MPPI_EINVAL;
   if (c.path == MPPI_PATH_PLAIN && c.precision != MPPI_PREC_FP32) return MPPI_EINVAL;
+  if (c.path == MPPI_PATH_FUSED) {
+    if (c.sdf_kind != MPPI_SDF_MLP || !fused_supported(c.precision, c.hidden, c.n_hidden)) return MPPI_EINVAL;
+    const int max_tiles = (c.K_max + fused_tile_rollouts(c.precision, c.hidden, c.G_max) - 1) /
+                          fused_tile_rollouts(c.precision, c.hidden, c.G_max);
+    if (fused_lds_bytes(c.precision, c.hidden, c.T_max, c.G_max, max_tiles) > kMaxLdsBytes) return MPPI_EINVAL;
+  }
   if (c.K_max < 1 || c.K_max > kMaxK || c.T_max < 1 || c.T_max > kMaxT || c.G_max < 1 || c.G_max > kMaxG)
     return MPPI_EINVAL;
   if (c.max_instances < 1 || c.max_inflight < 1 || c.queue_depth < 1) return MPPI_EINVAL;
@@ -775,7 +783,9 @@ int mppi_create(const mppi_config* cfg, const mppi_sdf_weights* w, mppi_engine**
     e->pool = (char*)c.device_pool;
     e->pool_bytes = c.device_pool_bytes;
   } else {
-    e->pool_bytes = c.hbm_budget_bytes;
+    // headroom above the admission budget for batch descriptor blocks and
+    // allocator fragmentation
+    e->pool_bytes = c.hbm_budget_bytes + std::max<uint64_t>(c.hbm_budget_bytes / 8, 16ull << 20);
     if (hipMalloc(&e->pool, e->pool_bytes) != hipSuccess) return bail(MPPI_ENOMEM);
     e->own_pool = true;
   }
@@ -1071,6 +1081,15 @@ void scheduler_loop(mppi_engine* e) {
         const uint64_t tadm = now_ns();
         int rc = stage(e, rs, true, true, false, b.st);
         hipStream_t st = e->streams[si];
+        if (rc == MPPI_ENOMEM && !e->inflight.empty()) {
+          // admitted by budget but the pool cannot place them yet: retry once
+          // a running batch has released its blocks
+          e->adm->requeue_front(adm);
+          lk.unlock();
+          std::this_thread::sleep_for(std::chrono::microseconds(20));
+          lk.lock();
+          continue;
+        }
         if (rc == MPPI_OK && timing) {
           hipEventCreate(&b.t0);
           hipEventCreate(&b.t1);

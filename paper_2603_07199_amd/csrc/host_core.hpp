@@ -102,7 +102,7 @@ inline SolveLayout solve_layout(int K, int T, int G, int H, bool fused, int n_ti
     L.Jpart = take(4ull * K);
     L.wt = take(8ull * K);
   } else {
-    L.partials = take(8ull * (2 + 4 * T) * n_tiles);
+    L.partials = take(8ull * (4 + 4 * T) * n_tiles);
     L.tiles_done = take(64);
   }
   L.total = o;
@@ -152,6 +152,15 @@ class Admission {
   void complete(uint64_t footprint) {
     in_use_ -= footprint;
     --inflight_;
+  }
+  // Undo admit() for items that could not be placed yet: back to the queue
+  // front, in their original order.
+  void requeue_front(const std::vector<AdmissionItem>& items) {
+    for (auto it = items.rbegin(); it != items.rend(); ++it) {
+      in_use_ -= it->footprint;
+      --inflight_;
+      q_.push_front(*it);
+    }
   }
   size_t queued() const { return q_.size(); }
   int inflight() const { return inflight_; }

@@ -34,12 +34,20 @@ struct FusedBatch {
   uint32_t* tile_counter;    // device work counter (zeroed by the launcher)
 };
 
-hipError_t launch_fused(const FusedBatch& b, const DeviceWeights& w, int max_T, hipStream_t s,
-                        hipEvent_t begin, hipEvent_t end);
+// n_solves descriptors, max_T / max_G over them, max_tiles = most tiles of
+// one solve.  begin/end (optional) bracket the fused kernel itself.
+hipError_t launch_fused(const FusedBatch& b, int n_solves, const DeviceWeights& w, int max_T, int max_G,
+                        int max_tiles, hipStream_t s, hipEvent_t begin, hipEvent_t end);
 
 // Rollouts per fused tile for a precision / width (the unit of work of the
 // persistent kernel).
 int fused_tile_rollouts(int precision, int H, int G);
+
+// Whether the fused kernel exists for this precision / width / depth, and the
+// LDS bytes one workgroup needs for the given horizon, gate count and tiles.
+bool fused_supported(int precision, int H, int n_hidden);
+size_t fused_lds_bytes(int precision, int H, int Tm, int Gm, int max_tiles);
+constexpr size_t kMaxLdsBytes = 160 * 1024;
 
 // Quantise and pack the hidden H x H layers for a low-precision variant
 // (BF16, BF16X2, FP8) in the fused kernel's operand order.  Returns an

@@ -160,6 +160,11 @@ int main() {
   q2.push({7, 1, 10}); q2.push({8, 1, 10}); q2.push({9, 2, 10});
   adm = q2.admit(none);
   assert(adm.size() == 2 && adm[0].ticket == 7 && adm[1].ticket == 9);
+  // requeue restores order and accounting
+  q2.requeue_front(adm);
+  assert(q2.in_use() == 0 && q2.inflight() == 0 && q2.queued() == 3);
+  adm = q2.admit(none);
+  assert(adm.size() == 2 && adm[0].ticket == 7 && adm[1].ticket == 9);
   // layout: regions are disjoint, aligned, and grow with K, T, G
   SolveLayout L = solve_layout(4096, 50, 4, 256, false, 0);
   assert(L.total % kAlign == 0 && L.upload_bytes <= L.result);

@@ -1,0 +1,115 @@
+"""Parity of the fused low-precision path with the FP64 oracle under the
+matching precision contract (the oracle rounds exactly what the kernel's
+matrix cores consume):
+
+* BF16X2 / BF16X3 (bfloat16 weights, split activations) against ``bf16w``:
+  residual activation error 2^-16 (X2) / 2^-24 (X3) relative, so u*_0 is gated
+  at the float32 tolerance 1e-4;
+* BF16 against ``bf16`` and FP8 against ``fp8``: activations rounded to 8 / 4
+  significant bits flip where the float32 and float64 values straddle a
+  rounding boundary, so the u*_0 error is reported and gated loosely.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import scenarios as sc
+from gpu_common import SIGMA_FLOOR, U0_TOL, require_gpu, say, u0_error
+from oracle.mppi import sample_controls
+from oracle.sdf import hidden_input_amax
+
+pytestmark = pytest.mark.gpu
+
+CONTRACT = {"bf16x2": "bf16w", "bf16x3": "bf16w", "bf16": "bf16", "fp8": "fp8"}
+U0_GATE = {"bf16x2": U0_TOL, "bf16x3": U0_TOL, "bf16": 2e-2, "fp8": 2e-1}
+
+
+def _act_scales(layers, W, b, probs):
+    """Static FP8 activation scales from oracle queries of the given problems."""
+    amax = np.zeros(len(layers) - 3)
+    for p in probs:
+        u = sample_controls(p, sc.MODEL, oracle.hover_sequence(p["T"], 0.37, 9.81))
+        pr, _, _ = oracle.rollout(p["x0"], u, p["dt"], 0.37, 9.81)
+        pts = (pr[:, 1:] + p["x0"][0:3]).reshape(-1, 3)
+        for g in range(p["G"]):
+            pg = (pts - p["gate_t"][g]) @ p["gate_R"][g]
+            amax = np.maximum(amax, hidden_input_amax(pg, p["gate_z"][g].astype(np.float64),
+                                                      [w.astype(np.float64) for w in W],
+                                                      [v.astype(np.float64) for v in b]))
+    return amax / 448.0
+
+
+def _engine(M, layers, precision, K_max, T_max, G_max, act_scale=None, wseed=0, bias=0.0):
+    W, b = sc.xavier_weights(layers, seed=wseed, bias_scale=bias)
+    wts = (W, b, act_scale) if act_scale is not None else (W, b)
+    eng = M.Engine(wts, sc.MODEL, K_max=K_max, T_max=T_max, G_max=G_max, hidden=layers[1],
+                   n_hidden=len(layers) - 2, precision=precision, path="fused", budget=512 << 20)
+    return eng, (W, b)
+
+
+@pytest.mark.parametrize("precision", ["bf16x2", "bf16x3", "bf16", "fp8"])
+def test_p1_fused_precision_variants(precision):
+    M = require_gpu()
+    layers = (67, 128, 128, 1)
+    W, b = sc.xavier_weights(layers, seed=0)
+    scales = None
+    if precision == "fp8":
+        scales = _act_scales(layers, W, b, [sc.config_problem("P1", 0, K=256)])
+    eng, w = _engine(M, layers, precision, 256, 20, 1, act_scale=scales)
+    for d_safe in (0.3, 1.0):
+        errs, errs32 = [], []
+        for seed in range(1, 9):
+            prob = sc.config_problem("P1", seed, d_safe=d_safe, instance_id=int(d_safe * 10) * 100 + seed)
+            ref = oracle.solve(prob, w, sc.MODEL, contract=CONTRACT[precision], act_scales=scales)
+            ref32 = oracle.solve(prob, w, sc.MODEL, contract="fp32")
+            out = eng.step(prob)
+            assert out["rc"] == 0, out["rc"]
+            assert abs(out["w"].sum() - 1.0) < 1e-12
+            errs.append(u0_error(out["u0"], ref["u0"]))
+            errs32.append(u0_error(out["u0"], ref32["u0"]))
+            dJ = np.abs(out["J"] - ref["J"])
+            if precision in ("bf16x2", "bf16x3"):
+                assert np.all(dJ <= 2e-5 * (np.abs(ref["J"]) + prob["Q_sdf"] * prob["T"] + 1.0)), dJ.max()
+        say(f"P1 fused {precision} d_safe={d_safe}: u0 err vs {CONTRACT[precision]} max {max(errs):.2e} "
+            f"median {np.median(errs):.2e}; vs fp32 max {max(errs32):.2e}")
+        assert max(errs) <= U0_GATE[precision]
+    eng.close()
+
+
+def test_p2_fused_bf16x2_full_size_and_determinism():
+    M = require_gpu()
+    layers = (67, 256, 256, 256, 1)
+    eng, w = _engine(M, layers, "bf16x2", 4096, 50, 4)
+    for seed in (1, 2):
+        prob = sc.config_problem("P2", seed, instance_id=seed)
+        ref = oracle.solve(prob, w, sc.MODEL, contract="bf16w")
+        out = eng.step(prob)
+        assert out["rc"] == 0
+        e = u0_error(out["u0"], ref["u0"])
+        dJ = np.abs(out["J"] - ref["J"])
+        say(f"P2 fused bf16x2 seed {seed}: u0 err {e:.2e}, max |dJ| {dJ.max():.2e}, ess {out['ess']:.1f}")
+        assert e <= U0_TOL
+        assert np.all(dJ <= 2e-5 * (np.abs(ref["J"]) + 50 * 50 + 1.0))
+    # same request twice (same explicit tick and nominal): bitwise equal
+    U = oracle.hover_sequence(50, 0.37, 9.81)
+    prob = sc.config_problem("P2", 3, instance_id=77, tick=5, U_nom=U)
+    a = eng.step(prob)
+    c = eng.step(prob)
+    assert np.array_equal(a["U_star"], c["U_star"]) and np.array_equal(a["J"], c["J"])
+    eng.close()
+
+
+def test_fused_ragged_shapes_and_gates():
+    M = require_gpu()
+    layers = (67, 256, 256, 1)
+    eng, w = _engine(M, layers, "bf16x3", 1000, 37, 8, wseed=4, bias=0.3)
+    for K, T, G, flags in ((1, 1, 1, 0), (17, 5, 3, 0), (999, 37, 8, 2), (250, 20, 5, 0)):
+        prob = sc.make_problem(K, T, G, rot="haar", start="moving", seed=K + T, d_safe=1.0,
+                               flags=flags, instance_id=K)
+        ref = oracle.solve(prob, w, sc.MODEL, contract="bf16w")
+        out = eng.step(prob)
+        assert out["rc"] == 0
+        e = u0_error(out["u0"], ref["u0"])
+        say(f"fused ragged K={K} T={T} G={G}: u0 err {e:.2e}")
+        assert e <= U0_TOL
+    eng.close()
