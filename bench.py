@@ -10,10 +10,12 @@ RNG tick advance on the device from step to step.
 Prints one JSON line: rollout-steps/s (value), per-step latency p50/p99, the
 roofline of the dominant kernel (HIP-event durations recorded by the library
 on its own stream), the FP32 plain one-solve-per-launch path on the same
-workload for comparison, and the FP64 oracle timed on the host cores.
+workload for comparison, a served leg (uneven requests arriving as a Poisson
+stream through mppi_submit / mppi_poll, with latency probes of the workload's
+shape) and the FP64 oracle timed on the host cores.
 
     python bench.py [--steps K] [--warmup W] [--path fused|plain]
-                    [--precision bf16x2|bf16|fp8|fp32] [--batch B]
+                    [--precision bf16x3|bf16x2|bf16|fp32] [--batch B]
 """
 from __future__ import annotations
 
@@ -106,6 +108,84 @@ def run_leg(M, path, precision, batch, steps, warmup):
     }
 
 
+def served_leg(M, precision, n_req, plain_subset=64):
+    """Uneven requests (K in {1024..8192}, T in {20..60}, G = 1, own instance
+    each) arriving as a Poisson stream (mean gap 50 us), every 16th replaced by
+    a probe of the benchmark shape (K=4096, T=50, G=4); served through
+    mppi_submit / mppi_poll.  Latency = completion - submission (host
+    monotonic clock).  The plain FP32 path runs the first plain_subset
+    requests one solve per launch, back to back, for comparison."""
+    reqs = sc.serving_requests(n_req=n_req)
+    probe = sc.config_problem("P2", 99)
+    items = []
+    for i, (arr, p) in enumerate(reqs):
+        if i % 16 == 15:
+            p = dict(probe, instance_id=p["instance_id"])
+        items.append((arr, p, i % 16 == 15))
+    W, b = sc.config_weights("P2")
+    eng = M.Engine((W, b), sc.MODEL, K_max=8192, T_max=60, G_max=4, hidden=256, n_hidden=3,
+                   precision=precision, path="fused", budget=8 << 30, queue_depth=4096,
+                   max_inflight=4096, max_instances=4096)
+    warm = [dict(items[0][1], instance_id=1 << 40)]
+    rc, t = eng.submit(warm[0])
+    while eng.poll(t, warm[0]["K"], warm[0]["T"])[0] == M.MPPI_PENDING:
+        time.sleep(1e-4)
+    # latency counts from the request's arrival time on the host monotonic
+    # clock (the clock the library stamps completions with)
+    tickets = []
+    t0 = time.monotonic_ns()
+    for arr, p, is_probe in items:
+        t_arr = t0 + int(arr * 1e9)
+        while time.monotonic_ns() < t_arr:
+            pass
+        rc, t = eng.submit(p)
+        if rc != 0:
+            raise RuntimeError(f"submit failed: {rc}")
+        tickets.append((t, p, is_probe, t_arr))
+    lat, lat_probe, done = [], [], {}
+    work = 0
+    t_first, t_last = None, None
+    while len(done) < len(tickets):
+        for t, p, is_probe, t_arr in tickets:
+            if t in done:
+                continue
+            rc, r = eng.poll(t, p["K"], p["T"], weights=False, costs=False)
+            if rc == M.MPPI_PENDING:
+                continue
+            if rc != 0:
+                raise RuntimeError(f"served solve failed: {rc}")
+            done[t] = True
+            ms = (r["t_done_ns"] - t_arr) * 1e-6
+            (lat_probe if is_probe else lat).append(ms)
+            work += p["K"] * p["T"]
+            t_first = t_arr if t_first is None else min(t_first, t_arr)
+            t_last = r["t_done_ns"] if t_last is None else max(t_last, r["t_done_ns"])
+    st = eng.stats()
+    eng.close()
+    span = (t_last - t_first) * 1e-9
+    out = {"requests": len(items), "batches": int(st["waves"]),
+           "rollout_steps_per_s": work / span, "span_s": span,
+           "offered_rollout_steps_per_s": work / items[-1][0],
+           "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+           "probe_latency_ms": {"p50": float(np.percentile(lat_probe, 50)),
+                                "p99": float(np.percentile(lat_probe, 99)), "n": len(lat_probe)}}
+    # the same kind of requests through the plain FP32 one-solve-per-launch path
+    sub = [p for _, p, _ in items[:plain_subset]]
+    pe = M.Engine((W, b), sc.MODEL, K_max=8192, T_max=60, G_max=4, hidden=256, n_hidden=3,
+                  precision="fp32", path="plain", budget=2 << 30, max_instances=4096)
+    pe.step(dict(sub[0], instance_id=1 << 40))
+    tp = time.perf_counter()
+    pw = 0
+    for p in sub:
+        r = pe.step(p, weights=False, costs=False)
+        if r["rc"] != 0:
+            raise RuntimeError(f"plain solve failed: {r['rc']}")
+        pw += p["K"] * p["T"]
+    out["fp32_plain_same_requests_rollout_steps_per_s"] = pw / (time.perf_counter() - tp)
+    pe.close()
+    return out
+
+
 def cpu_baseline():
     """The FP64 oracle on one full paper-scale solve (K = 4096, T = 50, G = 4)."""
     import torch
@@ -127,11 +207,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--path", default="plain", choices=["plain", "fused"])
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "bf16x2", "bf16x3", "fp8"])
+    ap.add_argument("--path", default="fused", choices=["plain", "fused"])
+    ap.add_argument("--precision", default="bf16x3", choices=["fp32", "bf16", "bf16x2", "bf16x3"])
     ap.add_argument("--batch", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
+    ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--served-requests", type=int, default=512)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
@@ -186,6 +268,8 @@ def main():
         out["fp32_plain"] = {"rollout_steps_per_s": ref["rollout_steps_per_s"],
                              "ms_per_step": ref["ms_per_step"],
                              "speedup": main_leg["rollout_steps_per_s"] / ref["rollout_steps_per_s"]}
+    if not args.no_served and args.path == "fused":
+        out["served"] = served_leg(M, args.precision, args.served_requests)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

@@ -170,9 +170,14 @@ __global__ __launch_bounds__(kThreads, 1) void k_fused(FusedBatch batch, DeviceW
   // Write this lane's 4 consecutive neurons (m0 .. m0+3) of row n to buffer buf.
   auto put_act = [&](int buf, int n, int m0, const float v[4], int layer_in) {
     if constexpr (PT::fp8) {
+      // saturate to the largest E4M3 value: the conversion alone turns values
+      // beyond the last rounding interval into NaN (activations are >= 0)
       const float inv = w.a_inv[layer_in];
-      uint32_t word = __builtin_amdgcn_cvt_pk_fp8_f32(v[0] * inv, v[1] * inv, 0, false);
-      word = __builtin_amdgcn_cvt_pk_fp8_f32(v[2] * inv, v[3] * inv, word, true);
+      float q[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) q[i] = fminf(v[i] * inv, 448.0f);
+      uint32_t word = __builtin_amdgcn_cvt_pk_fp8_f32(q[0], q[1], 0, false);
+      word = __builtin_amdgcn_cvt_pk_fp8_f32(q[2], q[3], word, true);
       *(uint32_t*)(lds + LL.act + ((size_t)buf * kRows + n) * ST8 + m0) = word;
     } else {
       float r[4] = {v[0], v[1], v[2], v[3]};

@@ -27,7 +27,7 @@ LAYERS = (67, 256, 256, 256, 1)
 
 def _engine(M, **kw):
     W, b = sc.xavier_weights(LAYERS, seed=0)
-    cfg = dict(K_max=4096, T_max=60, G_max=4, hidden=256, n_hidden=3, precision="bf16x2",
+    cfg = dict(K_max=4096, T_max=60, G_max=4, hidden=256, n_hidden=3, precision="bf16x3",
                path="fused", budget=1 << 30)
     cfg.update(kw)
     return M.Engine((W, b), sc.MODEL, **cfg), (W, b)
