@@ -20,6 +20,7 @@ shape) and the FP64 oracle timed on the host cores.
 from __future__ import annotations
 
 import argparse
+import ctypes
 import hashlib
 import json
 import os
@@ -202,6 +203,25 @@ def cpu_baseline():
                       f"67-256-256-256-1 decoder) in float64: {dt:.2f} s"}
 
 
+def _plain_copy(nbytes):
+    """One device-to-device copy of ``nbytes`` through the HIP runtime's copy
+    kernel: the known-size reference for the FETCH_SIZE / WRITE_SIZE counters.
+    Called through the HIP runtime that the library itself loaded, so a counter
+    run needs no torch in the process."""
+    hip = ctypes.CDLL("libamdhip64.so.7")
+    src, dst = ctypes.c_void_p(), ctypes.c_void_p()
+    for ptr in (src, dst):
+        if hip.hipMalloc(ctypes.byref(ptr), ctypes.c_size_t(nbytes)) != 0:
+            raise RuntimeError("hipMalloc failed for the calibration copy")
+    rc = hip.hipMemset(src, 1, ctypes.c_size_t(nbytes))
+    rc = rc or hip.hipMemcpy(dst, src, ctypes.c_size_t(nbytes), 3)      # device to device
+    rc = rc or hip.hipDeviceSynchronize()
+    hip.hipFree(src)
+    hip.hipFree(dst)
+    if rc != 0:
+        raise RuntimeError(f"calibration copy failed: {rc}")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -225,13 +245,7 @@ def main():
     from paper_2603_07199_amd import mppi as M
     M.load_library()
     if args.copy_mib:
-        import torch
-        n = args.copy_mib << 20
-        src = torch.ones(n // 4, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+        _plain_copy(args.copy_mib << 20)
 
     main_leg = run_leg(M, args.path, args.precision, args.batch, args.steps, args.warmup)
     queries = args.batch * K_ * T_ * G_

@@ -25,6 +25,7 @@
 #include <time.h>
 
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
@@ -144,6 +145,8 @@ struct mppi_engine {
   std::vector<InstInfo> inst;
   std::vector<double> hover;    // T_max x 4
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  char* pin[4] = {nullptr, nullptr, nullptr, nullptr};   // pinned staging per stream
+  size_t pin_cap[4] = {0, 0, 0, 0};
   mppi_stats stats{};
   std::atomic<int> sticky{0};
   std::mutex mu;                // guards everything above and below
@@ -418,18 +421,42 @@ void release_staged(mppi_engine* e, Staged& st, bool free_instances) {
   st.aux.bytes = 0;
 }
 
+// Pinned staging buffer of serving stream si with at least `bytes` capacity.
+// A stream's buffer is only rewritten once that stream's previous copies
+// have completed (one batch in flight per stream; blocking calls synchronise).
+char* pinned_for(mppi_engine* e, int si, size_t bytes) {
+  if (e->pin_cap[si] < bytes) {
+    if (hipStreamSynchronize(e->streams[si]) != hipSuccess) return nullptr;
+    if (e->pin[si]) hipHostFree(e->pin[si]);
+    e->pin[si] = nullptr;
+    e->pin_cap[si] = 0;
+    const size_t cap = std::max<size_t>(bytes + bytes / 2, 1 << 20);
+    if (hipHostMalloc((void**)&e->pin[si], cap, hipHostMallocDefault) != hipSuccess) return nullptr;
+    e->pin_cap[si] = cap;
+  }
+  return e->pin[si];
+}
+
 // Validate, bind instances, allocate, pack and upload a set of requests.
-// Every instance is held busy until the staged set is released.  On failure
-// nothing stays allocated or held.
+// The uploads are asynchronous copies on stream si from its pinned staging
+// buffer, so kernels enqueued after them on si see the data.  Every instance
+// is held busy until the staged set is released.  On failure nothing stays
+// allocated or held.
 int stage(mppi_engine* e, const std::vector<const mppi_request*>& reqs, bool want_w, bool want_J,
-          bool exports, Staged& out) {
+          bool exports, int si, Staged& out) {
   std::unordered_set<uint64_t> ids;
   for (auto* r : reqs)
     if (!ids.insert(r->instance_id).second) return MPPI_EINVAL;   // one solve per instance at a time
-  std::vector<char> host;
-  for (auto* r : reqs) {
-    double Lo[16];
-    int rc = validate(e, r, Lo);
+  auto fail = [&](int rc) {
+    release_staged(e, out, true);
+    out.solves.clear();
+    return rc;
+  };
+  std::vector<std::array<double, 16>> Lo(reqs.size());
+  size_t up_total = 0;
+  for (size_t i = 0; i < reqs.size(); ++i) {
+    const mppi_request* r = reqs[i];
+    int rc = validate(e, r, Lo[i].data());
     auto s = std::make_unique<Solve>();
     s->K = r->K;
     s->T = r->T;
@@ -445,34 +472,24 @@ int stage(mppi_engine* e, const std::vector<const mppi_request*>& reqs, bool wan
       if (!e->arena.alloc(s->lay.total, &s->off)) rc = MPPI_ENOMEM;
       else s->bytes = s->lay.total;
     }
-    if (rc != MPPI_OK) {
-      release_staged(e, out, true);
-      out.solves.clear();
-      return rc;
-    }
+    if (rc != MPPI_OK) return fail(rc);
     e->inst[s->slot].busy = true;
-    host.assign(s->lay.upload_bytes, 0);
-    char* base = e->pool + s->off;
-    pack_solve(e, r, s.get(), Lo, base, host.data());
-    const uint64_t ub = s->lay.upload_bytes;
+    up_total += align_up(s->lay.upload_bytes);
     out.solves.push_back(std::move(s));
-    hipError_t err = hipMemcpy(base, host.data(), ub, hipMemcpyHostToDevice);
-    if (err != hipSuccess) {
-      release_staged(e, out, true);
-      out.solves.clear();
-      return dev_fail(e, err);
-    }
   }
+  // fused launches also upload the descriptor array and the tile list
+  std::vector<int2> tiles;
+  uint64_t o_tiles = 0, o_cnt = 0;
+  Aux& a = out.aux;
   if (e->fused) {
-    std::vector<int2> tiles;
-    Aux& a = out.aux;
     for (size_t i = 0; i < out.solves.size(); ++i) {
       const Solve* s = out.solves[i].get();
-      const int R = s->desc.tile_rollouts;
-      for (int t = 0; t < s->desc.n_tiles; ++t) tiles.push_back(int2{(int)i, t * R});
+      const int R = tile_rollouts(e, s->G);
+      const int nt = (s->K + R - 1) / R;
+      for (int t = 0; t < nt; ++t) tiles.push_back(int2{(int)i, t * R});
       a.maxT = std::max(a.maxT, s->T);
       a.maxG = std::max(a.maxG, s->G);
-      a.maxTiles = std::max(a.maxTiles, s->desc.n_tiles);
+      a.maxTiles = std::max(a.maxTiles, nt);
     }
     // longest tiles first (work per tile grows with T G); ties keep solve order
     std::stable_sort(tiles.begin(), tiles.end(), [&](const int2& x, const int2& y) {
@@ -481,25 +498,34 @@ int stage(mppi_engine* e, const std::vector<const mppi_request*>& reqs, bool wan
       return sx->T * sx->G > sy->T * sy->G;
     });
     const size_t nS = out.solves.size();
-    const uint64_t o_tiles = align_up(sizeof(SolveDesc) * nS);
-    const uint64_t o_cnt = o_tiles + align_up(sizeof(int2) * tiles.size());
+    o_tiles = align_up(sizeof(SolveDesc) * nS);
+    o_cnt = o_tiles + align_up(sizeof(int2) * tiles.size());
     const uint64_t bytes = o_cnt + kAlign;
-    if (!e->arena.alloc(bytes, &a.off)) {
-      release_staged(e, out, true);
-      out.solves.clear();
-      return MPPI_ENOMEM;
-    }
+    if (!e->arena.alloc(bytes, &a.off)) return fail(MPPI_ENOMEM);
     a.bytes = bytes;
-    std::vector<char> ah(a.bytes, 0);
-    for (size_t i = 0; i < nS; ++i) memcpy(ah.data() + i * sizeof(SolveDesc), &out.solves[i]->desc, sizeof(SolveDesc));
-    memcpy(ah.data() + o_tiles, tiles.data(), sizeof(int2) * tiles.size());
+    up_total += bytes;
+  }
+  char* pin = pinned_for(e, si, up_total);
+  if (!pin) return fail(dev_fail(e, hipErrorOutOfMemory));
+  hipStream_t st = e->streams[si];
+  size_t po = 0;
+  for (size_t i = 0; i < reqs.size(); ++i) {
+    Solve* s = out.solves[i].get();
+    char* base = e->pool + s->off;
+    pack_solve(e, reqs[i], s, Lo[i].data(), base, pin + po);
+    const hipError_t err = hipMemcpyAsync(base, pin + po, s->lay.upload_bytes, hipMemcpyHostToDevice, st);
+    if (err != hipSuccess) return fail(dev_fail(e, err));
+    po += align_up(s->lay.upload_bytes);
+  }
+  if (e->fused) {
+    char* ah = pin + po;
+    memset(ah, 0, a.bytes);
+    for (size_t i = 0; i < out.solves.size(); ++i)
+      memcpy(ah + i * sizeof(SolveDesc), &out.solves[i]->desc, sizeof(SolveDesc));
+    memcpy(ah + o_tiles, tiles.data(), sizeof(int2) * tiles.size());
     char* ab = e->pool + a.off;
-    hipError_t err = hipMemcpy(ab, ah.data(), a.bytes, hipMemcpyHostToDevice);
-    if (err != hipSuccess) {
-      release_staged(e, out, true);
-      out.solves.clear();
-      return dev_fail(e, err);
-    }
+    const hipError_t err = hipMemcpyAsync(ab, ah, a.bytes, hipMemcpyHostToDevice, st);
+    if (err != hipSuccess) return fail(dev_fail(e, err));
     a.descs = (const SolveDesc*)ab;
     a.tiles = (const int2*)(ab + o_tiles);
     a.counter = (uint32_t*)(ab + o_cnt);
@@ -824,6 +850,8 @@ int mppi_destroy(mppi_engine* e) {
   if (e->wmem) hipFree(e->wmem);
   if (e->instU) hipFree(e->instU);
   if (e->instTick) hipFree(e->instTick);
+  for (char* p : e->pin)
+    if (p) hipHostFree(p);
   delete e;
   return MPPI_OK;
 }
@@ -836,7 +864,7 @@ int mppi_step(mppi_engine* e, const mppi_request* r, mppi_result* out) {
   const uint64_t t_submit = now_ns();
   Staged sg;
   const bool exports = out->samples || out->positions || out->sdf;
-  int rc = stage(e, {r}, out->weights != nullptr, out->costs != nullptr, exports, sg);
+  int rc = stage(e, {r}, out->weights != nullptr, out->costs != nullptr, exports, 0, sg);
   if (rc != MPPI_OK) return rc;
   hipStream_t st = e->streams[0];
   const bool timing = e->cfg.flags & MPPI_CFG_TIMING;
@@ -942,7 +970,11 @@ int mppi_batch_create(mppi_engine* e, const mppi_request* reqs, int32_t n, mppi_
   auto b = std::make_unique<mppi_batch>();
   std::vector<const mppi_request*> rs;
   for (int i = 0; i < n; ++i) rs.push_back(&reqs[i]);
-  int rc = stage(e, rs, true, true, false, b->st);
+  int rc = stage(e, rs, true, true, false, 0, b->st);
+  if (rc == MPPI_OK && hipStreamSynchronize(e->streams[0]) != hipSuccess) {
+    release_staged(e, b->st, true);
+    return dev_fail(e, hipErrorUnknown);
+  }
   if (rc != MPPI_OK) return rc;
   for (hipEvent_t* ev : {&b->t0, &b->t1, &b->s0, &b->s1})
     if (hipEventCreate(ev) != hipSuccess) {
@@ -1079,7 +1111,7 @@ void scheduler_loop(mppi_engine* e) {
         Inflight b;
         b.stream_idx = si;
         const uint64_t tadm = now_ns();
-        int rc = stage(e, rs, true, true, false, b.st);
+        int rc = stage(e, rs, true, true, false, si, b.st);
         hipStream_t st = e->streams[si];
         if (rc == MPPI_ENOMEM && !e->inflight.empty()) {
           // admitted by budget but the pool cannot place them yet: retry once
