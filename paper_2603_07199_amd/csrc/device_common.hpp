@@ -95,9 +95,19 @@ __device__ __forceinline__ void quad_step(RolloutState& s, const float u[4], flo
   const float wx = u[1], wy = u[2], wz = u[3];
   const float nrm = sqrtf(wx * wx + wy * wy + wz * wz);
   const float half = 0.5f * nrm * dt;
-  float sh, ch;
-  sincosf(half, &sh, &ch);
-  const float so = half < 1e-4f ? 0.5f * dt * (1.0f - half * half * (1.0f / 6.0f)) : sh / nrm;
+  float so, ch;
+  if (half < 0.25f) {
+    // Taylor series in half^2 (truncation < 3e-13): cos(half) and
+    // sin(half) / nrm = dt/2 sinc(half), no division, no range reduction
+    const float x2 = half * half;
+    ch = fmaf(x2, fmaf(x2, fmaf(x2, fmaf(x2, 1.0f / 40320.0f, -1.0f / 720.0f), 1.0f / 24.0f), -0.5f), 1.0f);
+    so = 0.5f * dt *
+         fmaf(x2, fmaf(x2, fmaf(x2, fmaf(x2, 1.0f / 362880.0f, -1.0f / 5040.0f), 1.0f / 120.0f), -1.0f / 6.0f), 1.0f);
+  } else {
+    float sh;
+    sincosf(half, &sh, &ch);
+    so = sh / nrm;
+  }
   const float rw = ch, rx = so * wx, ry = so * wy, rz = so * wz;
   s.q[0] = w * rw - x * rx - y * ry - z * rz;
   s.q[1] = w * rx + x * rw + y * rz - z * ry;

@@ -401,7 +401,6 @@ void pack_solve(mppi_engine* e, const mppi_request* r, Solve* s, const double Lo
   } else {
     const int R = tile_rollouts(e, G);
     d.partials = (double*)(base + lay.partials);
-    d.tiles_done = (uint32_t*)(base + lay.tiles_done);
     d.tile_rollouts = R;
     d.n_tiles = (K + R - 1) / R;
   }
@@ -756,7 +755,7 @@ int mppi_create(const mppi_config* cfg, const mppi_sdf_weights* w, mppi_engine**
     if (c.sdf_kind != MPPI_SDF_MLP || !fused_supported(c.precision, c.hidden, c.n_hidden)) return MPPI_EINVAL;
     const int max_tiles = (c.K_max + fused_tile_rollouts(c.precision, c.hidden, c.G_max) - 1) /
                           fused_tile_rollouts(c.precision, c.hidden, c.G_max);
-    if (fused_lds_bytes(c.precision, c.hidden, c.T_max, c.G_max, max_tiles) > kMaxLdsBytes) return MPPI_EINVAL;
+    if (fused_lds_bytes(c.precision, c.hidden, c.n_hidden, c.T_max, c.G_max, max_tiles) > kMaxLdsBytes) return MPPI_EINVAL;
   }
   if (c.K_max < 1 || c.K_max > kMaxK || c.T_max < 1 || c.T_max > kMaxT || c.G_max < 1 || c.G_max > kMaxG)
     return MPPI_EINVAL;

@@ -76,7 +76,7 @@ class Arena {
 // Byte layout of one solve's device block (descriptor, request data, buffers).
 struct SolveLayout {
   uint64_t desc, U, Rt, base, z, los;                // request part (uploaded)
-  uint64_t cfold, samples, pos, sdf, Jpart, J, wt, wn, result, partials, tiles_done;
+  uint64_t cfold, samples, pos, sdf, Jpart, J, wt, wn, result, partials;
   uint64_t upload_bytes, total;
 };
 
@@ -103,7 +103,6 @@ inline SolveLayout solve_layout(int K, int T, int G, int H, bool fused, int n_ti
     L.wt = take(8ull * K);
   } else {
     L.partials = take(8ull * (4 + 4 * T) * n_tiles);
-    L.tiles_done = take(64);
   }
   L.total = o;
   return L;

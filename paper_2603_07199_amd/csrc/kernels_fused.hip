@@ -1,34 +1,51 @@
 // Fused path: one persistent launch per batch of solves.
 //
-// Each workgroup (8 waves) repeatedly takes a tile of R rollouts of some solve
-// from a device work counter and runs the whole MPPI iteration on it
-// (Section IV-A/B):
+// Each workgroup repeatedly takes a tile of 16 rollouts of some solve from a
+// device work counter and runs the whole MPPI iteration on it (Section IV-A/B):
 //   noise + clipping   all threads over (rollout, step) pairs -> LDS;
 //   dynamics           one lane per rollout, serial over the horizon -> LDS
 //                      positions, control / alignment / progress costs;
-//   Gate-SDF decoder   32 query rows (rollout, step, gate) at a time; each wave
-//                      owns H/8 neurons of every hidden layer and keeps their
-//                      weights in VGPRs for the whole kernel; activations pass
-//                      through LDS (ping-pong buffers) as matrix-core operands;
-//                      the output dot and the max over gates end each chunk;
-//   tile partial       FP64 (rho_i, eta_i, eta2_i, S_i[T][4]) of the tile;
-//   merge              the workgroup that completes a solve's last tile
-//                      combines the partials in tile-index order (so results
-//                      do not depend on which workgroup ran which tile) and
-//                      writes U*, the weights, the warm start and the tick.
+//   Gate-SDF decoder   over the tile's (rollout, step, gate) query rows in
+//                      blocks of 16 rows, the hidden H x H layers on the matrix
+//                      cores, every wave's weight slice resident in VGPRs for
+//                      the whole kernel, activations passed through LDS;
+//   tile partial       FP64 (rho_i, eta_i, eta2_i, S_i[T][4]) of the tile.
+// A second kernel (one workgroup per solve) merges the partials in an order
+// fixed by the tile index (results do not depend on which workgroup ran which
+// tile or on what else was in the batch) and writes U*, the weights, the warm
+// start and the tick.  The kernel boundary publishes the partials; a
+// device-wide fence per tile instead costs tens of microseconds on a chip
+// whose XCDs have separate L2 caches.
+//
+// Decoder schedule (8 waves).  With one hidden H x H layer every wave owns
+// H/8 of its neurons; with two, waves 0-3 own H/4 neurons each of the first
+// and waves 4-7 of the second.  Blocks of 16 rows flow through a software
+// pipeline; in step s
+//   wave 0          gate-frame points of block s
+//   every wave      layer 1 (vector units) of block s-1, H/8 neurons each
+//   owners of l     matrix-core products of layer l on block s-2-2l into one
+//                   of two register accumulator sets, and the activation
+//                   epilogue (softplus, bf16 split / output dot) of block
+//                   s-3-2l from the other set
+//   last wave       output sum, max over gates and hinge of block s-2-2L
+//                   (L hidden H x H layers)
+// with one workgroup barrier per step.  A wave's products and its epilogue
+// work on different blocks, so the matrix cores and the vector units overlap
+// inside each wave.
 //
 // Precision variants of the hidden layers (FP32 accumulation throughout):
 //   BF16    weights and activations rounded to bfloat16;
 //   BF16X2  bfloat16 weights, activations split a = hi + lo (two products);
-//   BF16X3  bfloat16 weights, a = hi + mid + lo (three products);
+//   BF16X3  bfloat16 weights, a = hi + mid + lo exactly (three products);
 //   FP8     OCP E4M3 weights with a per-layer scale, E4M3 activations with a
-//           static per-layer scale.
+//           static per-layer scale (saturating).
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <string.h>
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <type_traits>
 
 #include "device_common.hpp"
@@ -39,11 +56,12 @@ namespace mppi {
 
 using f32x4 = __attribute__((ext_vector_type(4))) float;
 using bf16x8 = __attribute__((ext_vector_type(8))) __bf16;
+using bf16x2v = __attribute__((ext_vector_type(2))) __bf16;
 
-constexpr int kWaves = 8;
+constexpr int kWaves = 8;            // waves per workgroup
 constexpr int kThreads = 64 * kWaves;
-constexpr int kRows = 32;     // query rows per chunk (two 16-row MFMA blocks)
-constexpr int kTileR = 16;    // rollouts per tile
+constexpr int kTileR = 16;           // rollouts per tile
+constexpr int kRows = 16;            // query rows per pipeline block
 __host__ __device__ constexpr int kPartStride(int T) { return 4 + 4 * T; }
 
 enum { P_BF16 = 1, P_BF16X2 = 2, P_FP8 = 3, P_BF16X3 = 4 };
@@ -54,154 +72,534 @@ template <> struct PrecTraits<P_BF16X2> { static constexpr int splits = 2; stati
 template <> struct PrecTraits<P_BF16X3> { static constexpr int splits = 3; static constexpr bool fp8 = false; };
 template <> struct PrecTraits<P_FP8> { static constexpr int splits = 1; static constexpr bool fp8 = true; };
 
-__device__ __forceinline__ uint16_t bf16_bits(float v) { return __builtin_bit_cast(uint16_t, (__bf16)v); }
-__device__ __forceinline__ float bf16_val(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+// max(x, 0) as one integer max on the bit pattern (negative floats, -0
+// included, are negative integers); a float max would first quiet a
+// possible signalling NaN, one more instruction per activation.
+__device__ __forceinline__ float relu_bits(float x) {
+  const int i = __float_as_int(x);
+  return __int_as_float(i > 0 ? i : 0);
+}
 
 // softplus with the hardware base-2 exponential and logarithm:
 // max(x, 0) + ln2 * log2(1 + 2^(-|x| log2 e)); absolute error ~1e-7.
 __device__ __forceinline__ float softplus_fast(float x) {
   const float e = __builtin_amdgcn_exp2f(-fabsf(x) * 1.4426950408889634f);
-  return fmaf(__builtin_amdgcn_logf(1.0f + e), 0.6931471805599453f, fmaxf(x, 0.0f));
+  return fmaf(__builtin_amdgcn_logf(1.0f + e), 0.6931471805599453f, relu_bits(x));
 }
 
-// LDS activation row stride in elements (bf16) / bytes (fp8): pad keeps
+// LDS activation row stride in elements (bf16) / bytes (fp8): the pad keeps
 // 16-byte operand reads of 16 consecutive rows on distinct banks.
 template <int H> __host__ __device__ constexpr int act_stride_bf16() { return H + 8; }
 template <int H> __host__ __device__ constexpr int act_stride_fp8() { return H + 16; }
 
+// Bytes of one activation buffer (all split terms) of kRows rows.
 template <int P, int H>
-__host__ __device__ constexpr size_t act_bytes() {
-  return PrecTraits<P>::fp8 ? (size_t)2 * kRows * act_stride_fp8<H>()
-                            : (size_t)2 * PrecTraits<P>::splits * kRows * act_stride_bf16<H>() * 2;
+__host__ __device__ constexpr size_t act_buf_bytes() {
+  return PrecTraits<P>::fp8 ? (size_t)kRows * act_stride_fp8<H>()
+                            : (size_t)PrecTraits<P>::splits * kRows * act_stride_bf16<H>() * 2;
 }
 
 struct FusedLds {
-  size_t act, w1p, hb, wo, cf, rt, base, los, samp, dp, hinge, pts, opart, jl, wt, fac, misc, total;
+  size_t act, w1p, hb, wo, cf, rt, base, los, dp, hinge, pts, opart, jl, wt, fac, misc, total;
 };
 
-template <int P, int H>
+// The activation buffers (input of hidden layer l, block parity p) share
+// their space with the tile's control samples, which live only in the tile
+// prologue (dynamics) and epilogue (weighted sums), outside the decoder.
+template <int P, int H, int NHH>
 __host__ __device__ FusedLds fused_lds(int Tm, int Gm, int max_tiles) {
+  constexpr int WPL = kWaves / NHH;
   FusedLds L{};
   size_t o = 0;
   auto take = [&](size_t b) { const size_t r = o; o = (o + b + 15) / 16 * 16; return r; };
-  L.act = take(act_bytes<P, H>());
+  const size_t acts = 2 * NHH * act_buf_bytes<P, H>();
+  const size_t samp = sizeof(float) * 4 * kTileR * Tm;
+  // fixed-size tables and the activation buffers first (compile-time
+  // offsets for everything the decoder steps touch), then per-solve tables
   L.w1p = take(sizeof(float) * 4 * H);
-  L.hb = take(sizeof(float) * 2 * H);      // hidden biases (up to 2 layers)
-  L.wo = take(sizeof(float) * H);          // output row
+  L.hb = take(sizeof(float) * NHH * H);
+  L.wo = take(sizeof(float) * H);
+  L.pts = take(sizeof(float) * 4 * kRows * 2);
+  L.opart = take(sizeof(float) * 2 * WPL * kRows * 4);
+  L.jl = take(sizeof(float) * 2 * kTileR);
+  L.wt = take(sizeof(double) * (kTileR + 4));
+  L.misc = take(64);
+  L.act = take(acts > samp ? acts : samp);
   L.cf = take(sizeof(float) * Gm * H);
   L.rt = take(sizeof(float) * 9 * Gm);
   L.base = take(sizeof(float) * 3 * Gm * (Tm + 1));
   L.los = take(sizeof(float) * 2 * Tm);
-  L.samp = take(sizeof(float) * 4 * kTileR * Tm);
   L.dp = take(sizeof(float) * 3 * kTileR * (Tm + 1));
   L.hinge = take(sizeof(float) * kTileR * Tm);
-  L.pts = take(sizeof(float) * 4 * kRows);
-  L.opart = take(sizeof(float) * kWaves * kRows);
-  L.jl = take(sizeof(float) * 2 * kTileR);
-  L.wt = take(sizeof(double) * (kTileR + 4));
   L.fac = take(sizeof(double) * max_tiles);
-  L.misc = take(64);
   L.total = o;
   return L;
 }
 
-// Per-lane weight fragment of hidden layer l (A operand, 16x16x32): wave w,
-// neuron block mb, K-step ks; lane holds W[m][32 ks + 8 (lane / 16) + j], j < 8,
-// m = w H/8 + 16 mb + lane % 16.  BF16: 16 bytes; FP8: 8 bytes.
+// Per-lane weight fragment of hidden layer l (A operand, 16x16x32): neuron
+// block nb (16 neurons), K-step ks; the lane holds
+// W[16 nb + lane % 16][32 ks + 8 (lane / 16) + j], j < 8.
+// BF16: 16 bytes; FP8: 8 bytes.
 template <int H>
-__host__ __device__ constexpr size_t frag_index(int l, int w, int mb, int ks, int lane) {
-  return ((((size_t)l * kWaves + w) * (H / 8 / 16) + mb) * (H / 32) + ks) * 64 + lane;
+__host__ __device__ constexpr size_t frag_index(int l, int nb, int ks, int lane) {
+  return (((size_t)l * (H / 16) + nb) * (H / 32) + ks) * 64 + lane;
+}
+
+// Shared-memory views of one workgroup.
+struct Views {
+  char* act;
+  float *samp, *w1p, *hb, *wo, *cf, *rt, *base, *los, *dp, *hinge, *pts, *opart, *jl;
+  double *wt, *fac;
+  int* misc;
+};
+
+template <int P, int H, int NHH>
+__device__ __forceinline__ Views make_views(char* lds, int Tm, int Gm, int max_tiles) {
+  const FusedLds L = fused_lds<P, H, NHH>(Tm, Gm, max_tiles);
+  Views v;
+  v.act = lds + L.act;
+  v.samp = (float*)(lds + L.act);
+  v.w1p = (float*)(lds + L.w1p);
+  v.hb = (float*)(lds + L.hb);
+  v.wo = (float*)(lds + L.wo);
+  v.cf = (float*)(lds + L.cf);
+  v.rt = (float*)(lds + L.rt);
+  v.base = (float*)(lds + L.base);
+  v.los = (float*)(lds + L.los);
+  v.dp = (float*)(lds + L.dp);
+  v.hinge = (float*)(lds + L.hinge);
+  v.pts = (float*)(lds + L.pts);
+  v.opart = (float*)(lds + L.opart);
+  v.jl = (float*)(lds + L.jl);
+  v.wt = (double*)(lds + L.wt);
+  v.fac = (double*)(lds + L.fac);
+  v.misc = (int*)(lds + L.misc);
+  return v;
+}
+
+// Two floats -> packed bfloat16 pair (round to nearest even), and back.
+__device__ __forceinline__ uint32_t pack_bf16(float a, float b) {
+  const bf16x2v t = {(__bf16)a, (__bf16)b};
+  return __builtin_bit_cast(uint32_t, t);
+}
+__device__ __forceinline__ float bf16_lo(uint32_t w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float bf16_hi(uint32_t w) { return __uint_as_float(w & 0xFFFF0000u); }
+
+// Byte offset of (row n, neuron / K index m) inside one split term of an
+// activation buffer, and the byte size of one split term.
+template <int P, int H>
+__host__ __device__ constexpr uint32_t act_off(int n, int m) {
+  return PrecTraits<P>::fp8 ? (uint32_t)(n * act_stride_fp8<H>() + m) : (uint32_t)(n * act_stride_bf16<H>() + m) * 2u;
+}
+template <int P, int H>
+__host__ __device__ constexpr uint32_t act_term_bytes() {
+  return PrecTraits<P>::fp8 ? (uint32_t)(kRows * act_stride_fp8<H>()) : (uint32_t)(kRows * act_stride_bf16<H>() * 2);
+}
+
+// Write 4 consecutive neurons of one row, at byte offset `off` of activation
+// buffer `buf`, as the operand of the next layer.  bf16 splits:
+// a = hi + (mid) + (lo) with each term the round-to-nearest bfloat16 of the
+// remainder; for three terms the sum is exact.
+template <int P, int H>
+__device__ __forceinline__ void put_act(char* buf, uint32_t off, const float v[4], float inv) {
+  using PT = PrecTraits<P>;
+  if constexpr (PT::fp8) {
+    // saturate to the largest E4M3 value: the conversion alone turns values
+    // beyond the last rounding interval into NaN (activations are >= 0)
+    float q[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) q[i] = fminf(v[i] * inv, 448.0f);
+    uint32_t word = __builtin_amdgcn_cvt_pk_fp8_f32(q[0], q[1], 0, false);
+    word = __builtin_amdgcn_cvt_pk_fp8_f32(q[2], q[3], word, true);
+    *(uint32_t*)(buf + off) = word;
+  } else {
+    constexpr int NS = PT::splits;
+    float r0 = v[0], r1 = v[1], r2 = v[2], r3 = v[3];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const uint32_t w01 = pack_bf16(r0, r1), w23 = pack_bf16(r2, r3);
+      *(uint2*)(buf + off + s * act_term_bytes<P, H>()) = make_uint2(w01, w23);
+      if (s + 1 < NS) {
+        r0 -= bf16_lo(w01);
+        r1 -= bf16_hi(w01);
+        r2 -= bf16_lo(w23);
+        r3 -= bf16_hi(w23);
+      }
+    }
+  }
+}
+
+template <int P>
+using FragT = typename std::conditional<PrecTraits<P>::fp8, long, bf16x8>::type;
+
+// Gate-frame point of row `row` of block c (kRows / G positions per block).
+__device__ __forceinline__ void chunk_point(const Views& V, const SolveDesc& d, int c, int row, int npos,
+                                            float* out4) {
+  const int G = d.G, T = d.T;
+  const int Pc = kRows / G;
+  const int p = row / G, g = row - p * G;
+  const int q = c * Pc + p;
+  float px = 0.0f, py = 0.0f, pz = 0.0f;
+  if (p < Pc && q < npos) {
+    const int kl = q / T, t = q - kl * T;
+    const int tp = t + (int)d.q_off;
+    const float* dpp = V.dp + 3 * (kl * (T + 1) + tp);
+    const float* R = V.rt + 9 * g;
+    const float* b = V.base + 3 * (g * (T + 1) + tp);
+    px = fmaf(R[0], dpp[0], fmaf(R[1], dpp[1], fmaf(R[2], dpp[2], b[0])));
+    py = fmaf(R[3], dpp[0], fmaf(R[4], dpp[1], fmaf(R[5], dpp[2], b[1])));
+    pz = fmaf(R[6], dpp[0], fmaf(R[7], dpp[1], fmaf(R[8], dpp[2], b[2])));
+  }
+  out4[0] = px;
+  out4[1] = py;
+  out4[2] = pz;
+  out4[3] = (float)((p < Pc) ? g : 0);
+}
+
+// Output of row `row` of block c (called by lanes 0 .. kRows-1 of one wave):
+// sum of the per-lane partials of the last layer's owners, max over each
+// position's gates, hinge into the tile's table.
+template <int WPL>
+__device__ __forceinline__ void chunk_reduce(const Views& V, const SolveDesc& d, const float* opart, float bout,
+                                             int c, int row, int npos) {
+  const int G = d.G;
+  float acc = 0.0f;
+#pragma unroll
+  for (int w = 0; w < WPL; ++w) {
+    const float4 o = *(const float4*)(opart + 4 * (w * kRows + row));
+    acc += (o.x + o.y) + (o.z + o.w);
+  }
+  const float sv = acc + bout;
+  const int Pc = kRows / G;
+  const int p = row / G;
+  float best = sv;
+  for (int g = 1; g < G; ++g) {
+    const float o = __shfl(sv, p * G + g, 64);
+    if (p * G + g < kRows) best = fmaxf(best, o);
+  }
+  const int q = c * Pc + p;
+  if (row == p * G && p < Pc && q < npos) V.hinge[q] = fmaxf(0.0f, d.d_safe - best);
+}
+
+// Clipped control samples of the tile (Section IV-A) into V.samp.
+__device__ __forceinline__ void tile_noise(const Views& V, const SolveDesc& d, int k0, int Re, uint32_t tick) {
+  const int T = d.T;
+  for (int i = threadIdx.x; i < Re * T; i += kThreads) {
+    const int kl = i / T, t = i - kl * T;
+    float u[4];
+    sample_control(d, (uint32_t)(k0 + kl), (uint32_t)t, tick, u);
+    *(float4*)(V.samp + 4 * i) = make_float4(u[0], u[1], u[2], u[3]);
+  }
+}
+
+// Per-tile tables, noise and dynamics (all threads of the workgroup call it).
+__device__ void tile_prologue(const Views& V, const SolveDesc& d, int k0, int Re, uint32_t tick, int H) {
+  const int tid = threadIdx.x, T = d.T, G = d.G;
+  for (int i = tid; i < G * H; i += kThreads) V.cf[i] = d.cfold[i];
+  for (int i = tid; i < 9 * G; i += kThreads) V.rt[i] = d.Rt[i];
+  for (int i = tid; i < 3 * G * (T + 1); i += kThreads) V.base[i] = d.base[i];
+  if (d.Q_vis != 0.0f)
+    for (int i = tid; i < 2 * T; i += kThreads) V.los[i] = d.los[i];
+  tile_noise(V, d, k0, Re, tick);
+  __syncthreads();
+  // dynamics: one lane per rollout
+  if (tid < Re) {
+    RolloutState s;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) { s.dp[i] = 0.0f; s.dv[i] = 0.0f; }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) s.q[i] = d.q0[i];
+    float* dpk = V.dp + 3 * tid * (T + 1);
+    dpk[0] = dpk[1] = dpk[2] = 0.0f;
+    float Jc = 0.0f, Jv = 0.0f;
+    for (int t = 0; t < T; ++t) {
+      const float4 uu = *(const float4*)(V.samp + 4 * (tid * T + t));
+      const float u[4] = {uu.x, uu.y, uu.z, uu.w};
+      Jc = fmaf(u[0], u[0], fmaf(u[1], u[1], fmaf(u[2], u[2], fmaf(u[3], u[3], Jc))));
+      if (d.Q_vis != 0.0f) Jv += alignment_term(s.q, V.los[2 * t] - s.dp[0], V.los[2 * t + 1] - s.dp[1]);
+      quad_step(s, u, d.dt, d.inv_mass, d.gravity);
+      dpk[3 * (t + 1) + 0] = s.dp[0];
+      dpk[3 * (t + 1) + 1] = s.dp[1];
+      dpk[3 * (t + 1) + 2] = s.dp[2];
+    }
+    const float Jg = s.dp[0] * s.dp[0] + s.dp[1] * s.dp[1] + s.dp[2] * s.dp[2] +
+                     2.0f * (s.dp[0] * d.fprog[0] + s.dp[1] * d.fprog[1] + s.dp[2] * d.fprog[2]);
+    V.jl[tid] = d.Q_gate * Jg + d.R_u * Jc + d.Q_vis * Jv;
+  }
+  __syncthreads();
+}
+
+// Sum over the 64 lanes of a wave by a fixed butterfly: every lane gets the
+// same, schedule-independent result.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+
+// Per-rollout costs and the tile's FP64 partial (rho_i, eta_i, eta2_i,
+// S_i[T][4]) with weights relative to the tile's own minimum.  The sums run in
+// an order fixed by the rollout index.
+__device__ void tile_epilogue(const Views& V, const SolveDesc& d, int k0, int Re, uint32_t tick) {
+  const int tid = threadIdx.x, T = d.T;
+  // the decoder reused the samples' space: draw them again (same counters)
+  tile_noise(V, d, k0, Re, tick);
+  {
+    // hinge sum of rollout k over its T steps: 32 lanes per rollout
+    const int k = tid >> 5, part = tid & 31;
+    float hs = 0.0f;
+    for (int t = part; t < T; t += 32) hs += V.hinge[k * T + t];
+#pragma unroll
+    for (int m = 16; m >= 1; m >>= 1) hs += __shfl_xor(hs, m, 64);
+    if (part == 0 && k < Re) {
+      const float J = V.jl[k] + d.Q_sdf * hs;
+      V.jl[kTileR + k] = J;
+      d.J[k0 + k] = J;
+    }
+  }
+  __syncthreads();
+  if (tid < kTileR) {
+    double rho = INFINITY;
+    for (int k = 0; k < Re; ++k) {
+      const float J = V.jl[kTileR + k];
+      if (isfinite(J)) rho = fmin(rho, (double)J);
+    }
+    const float J = tid < Re ? V.jl[kTileR + tid] : NAN;
+    V.wt[tid] = (isfinite(J) && isfinite(rho)) ? exp(-((double)J - rho) * d.inv_lambda) : 0.0;
+    if (tid == 0) V.wt[kTileR] = rho;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double eta = 0.0, eta2 = 0.0;
+    for (int k = 0; k < kTileR; ++k) {
+      eta += V.wt[k];
+      eta2 += V.wt[k] * V.wt[k];
+    }
+    V.wt[kTileR + 1] = eta;
+    V.wt[kTileR + 2] = eta2;
+  }
+  __syncthreads();
+  double* part = d.partials + (size_t)(k0 / d.tile_rollouts) * kPartStride(T);
+  if (tid < 3) part[tid] = V.wt[kTileR + tid];
+  for (int i = tid; i < 4 * T; i += kThreads) {
+    double sacc = 0.0;
+    for (int k = 0; k < Re; ++k) sacc = fma(V.wt[k], (double)V.samp[4 * (k * T) + i], sacc);
+    part[4 + i] = sacc;
+  }
+}
+
+// Ends a basic block: a branch on a value the compiler cannot see (always
+// zero), with a memory clobber.  Code is not moved across it, so each part of
+// a step keeps its place in the wave's instruction stream and its own
+// register demand.
+__device__ __forceinline__ void sched_fence() {
+  int zz;
+  asm volatile("s_mov_b32 %0, 0" : "=s"(zz) : : "memory");
+  if (zz) asm volatile("s_nop 0");
+}
+
+template <int P>
+using BFragT = typename std::conditional<PrecTraits<P>::fp8, long, bf16x8>::type;
+
+// B operands (16 rows x 32 K of every split term) of K-step ks from `in`;
+// `off` is the lane's byte offset act_off(row, 8 (lane / 16)).
+template <int P, int H>
+__device__ __forceinline__ void read_operands(const char* in, uint32_t off, int ks,
+                                              BFragT<P> (&b)[PrecTraits<P>::splits]) {
+  constexpr int NS = PrecTraits<P>::splits;
+#pragma unroll
+  for (int sp = 0; sp < NS; ++sp) {
+    if constexpr (PrecTraits<P>::fp8) b[sp] = *(const long*)(in + off + 32 * ks);
+    else b[sp] = __builtin_bit_cast(bf16x8, *(const uint4*)(in + off + sp * act_term_bytes<P, H>() + 64 * ks));
+  }
+}
+
+// Matrix-core part of a step: acc = bias + W(owned) x in^T for 16 rows, one
+// scheduling region per K-step with the next K-step's operands read ahead.
+// b0 holds the operands of K-step 0 on entry.
+template <int P, int H, int OWN, int MB>
+__device__ __forceinline__ void products(const char* in, uint32_t boff, const float* hb, int gw, int h,
+                                         const FragT<P> (&wreg)[MB][H / 32], BFragT<P> (&b0)[PrecTraits<P>::splits],
+                                         f32x4 (&acc)[MB]) {
+  using PT = PrecTraits<P>;
+  constexpr int NS = PT::splits;
+  constexpr int KS = H / 32;
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb) {
+    if constexpr (PT::fp8) acc[mb] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    else acc[mb] = *(const f32x4*)(hb + OWN * H + 16 * (gw * MB + mb) + 4 * h);
+  }
+  BFragT<P> bn[NS];
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {
+    if (ks + 1 < KS) read_operands<P, H>(in, boff, ks + 1, bn);
+#pragma unroll
+    for (int sp = 0; sp < NS; ++sp)
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) {
+        if constexpr (PT::fp8) acc[mb] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(wreg[mb][ks], b0[sp], acc[mb], 0, 0, 0);
+        else acc[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wreg[mb][ks], b0[sp], acc[mb], 0, 0, 0);
+      }
+#pragma unroll
+    for (int sp = 0; sp < NS; ++sp) b0[sp] = bn[sp];
+    sched_fence();
+  }
+}
+
+// Vector part of a step: the epilogue of the owned layer from acc (softplus,
+// then the next layer's operand in `out`, or for the last layer this lane's
+// share of the output dot in `opart`), and layer 1 for this wave's neurons of
+// the block whose gate-frame points are `pts`, into `l1out`.
+template <int P, int H, int NHH, int OWN, int MB>
+__device__ __forceinline__ void vector_work(const f32x4 (&acc)[MB], char* out, char* l1out, float* opart,
+                                            const float* pts, const float* cf, const float* w1p, const float* hb,
+                                            const float* wo, const DeviceWeights& w, int wave, int gw, int h,
+                                            int nl, float scale_own) {
+  using PT = PrecTraits<P>;
+  constexpr int L1N = H / kWaves;   // layer-1 neurons per wave
+  const int e0 = 16 * gw * MB + 4 * h;          // first owned neuron of this lane
+  const uint32_t eoff = act_off<P, H>(nl, e0);
+  float op = 0.0f;
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb) {
+    float v[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      v[i] = softplus_fast(PT::fp8 ? fmaf(acc[mb][i], scale_own, hb[OWN * H + e0 + 16 * mb + i]) : acc[mb][i]);
+    if constexpr (OWN + 1 < NHH) {
+      put_act<P, H>(out, eoff + act_off<P, H>(0, 16 * mb), v, PT::fp8 ? w.a_inv[OWN + 1] : 1.0f);
+    } else {
+      const float4 o4 = *(const float4*)(wo + e0 + 16 * mb);
+      op = fmaf(o4.x, v[0], fmaf(o4.y, v[1], fmaf(o4.z, v[2], fmaf(o4.w, v[3], op))));
+    }
+    if (mb & 1) sched_fence();
+  }
+  if constexpr (OWN + 1 == NHH) opart[(gw * kRows + nl) * 4 + h] = op;
+  const float4 pt = *(const float4*)(pts + 4 * nl);
+  const int g = (int)pt.w;
+  const int l0 = wave * L1N + 4 * h;            // first layer-1 neuron of this lane
+  const uint32_t loff = act_off<P, H>(nl, l0);
+#pragma unroll
+  for (int j = 0; j < L1N / 16; ++j) {
+    // gate-frame point . W1 + folded latent term
+    const float4 c4 = *(const float4*)(cf + g * H + l0 + 16 * j);
+    const float cc[4] = {c4.x, c4.y, c4.z, c4.w};
+    float v[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const float4 wv = *(const float4*)(w1p + 4 * (l0 + 16 * j + i));
+      v[i] = softplus_fast(fmaf(wv.x, pt.x, fmaf(wv.y, pt.y, fmaf(wv.z, pt.z, cc[i]))));
+    }
+    put_act<P, H>(l1out, loff + act_off<P, H>(0, 16 * j), v, PT::fp8 ? w.a_inv[0] : 1.0f);
+  }
+}
+
+// One pipeline step (see the schedule at the top) of a wave that owns hidden
+// layer OWN; PAR is the parity of the step index.  The products of block
+// s-2-2 OWN read activation buffer (OWN, PAR) into acc[PAR]; the epilogue of
+// block s-3-2 OWN reads acc[1-PAR] (the previous step's products) and writes
+// buffer (OWN+1, 1-PAR) or the output partials of parity 1-PAR; layer 1 of
+// block s-1 goes to buffer (0, 1-PAR).  The two waves that share a SIMD run
+// the two parts in opposite order (MFIRST: products first), so that one
+// wave's matrix-core work runs beside the other's vector work.  Blocks outside
+// the tile's range run on stale data whose results are never read.
+template <int P, int H, int NHH, int OWN, int PAR, bool MFIRST, int MB>
+__device__ __forceinline__ void pipeline_step(const Views& V, const DeviceWeights& w, int wave, int gw, int h,
+                                              int nl, float scale_own, const FragT<P> (&wreg)[MB][H / 32],
+                                              f32x4 (&acc)[2][MB]) {
+  constexpr int WPL = kWaves / NHH;
+  constexpr size_t AB = act_buf_bytes<P, H>();
+  const char* in = V.act + (2 * OWN + PAR) * AB;
+  char* out = V.act + (2 * (OWN + 1 < NHH ? OWN + 1 : 0) + 1 - PAR) * AB;
+  char* l1out = V.act + (1 - PAR) * AB;
+  float* op = V.opart + (1 - PAR) * WPL * kRows * 4;
+  const float* pts = V.pts + 4 * (1 - PAR) * kRows;
+  const uint32_t boff = act_off<P, H>(nl, 8 * h);
+  BFragT<P> b0[PrecTraits<P>::splits];
+  if constexpr (MFIRST) {
+    read_operands<P, H>(in, boff, 0, b0);
+    products<P, H, OWN, MB>(in, boff, V.hb, gw, h, wreg, b0, acc[PAR]);
+    vector_work<P, H, NHH, OWN, MB>(acc[1 - PAR], out, l1out, op, pts, V.cf, V.w1p, V.hb, V.wo, w, wave, gw, h, nl,
+                                    scale_own);
+  } else {
+    read_operands<P, H>(in, boff, 0, b0);
+    vector_work<P, H, NHH, OWN, MB>(acc[1 - PAR], out, l1out, op, pts, V.cf, V.w1p, V.hb, V.wo, w, wave, gw, h, nl,
+                                    scale_own);
+    sched_fence();
+    products<P, H, OWN, MB>(in, boff, V.hb, gw, h, wreg, b0, acc[PAR]);
+  }
+}
+
+// The decoder over one tile's blocks for a wave that owns hidden layer OWN.
+// Activation buffer (l, p) is the input of hidden layer l for blocks of
+// parity p.  Every wave runs the same number of steps and barriers.
+template <int P, int H, int NHH, int OWN, bool MFIRST, int MB>
+__device__ __forceinline__ void decoder_tile(const Views& V, const SolveDesc& d, const DeviceWeights& w, int wave,
+                                             int lane, int gw, int h, int nl, float scale_own,
+                                             const FragT<P> (&wreg)[MB][H / 32], int npos, int nblk) {
+  constexpr int WPL = kWaves / NHH;
+  constexpr int lag = 2 + 2 * NHH;    // step at which a block's output is reduced
+  const int nsteps = nblk + lag;
+  f32x4 acc[2][MB];
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) acc[p][mb] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  auto edges = [&](int st, int par) {
+    if (wave == 0 && lane < kRows) chunk_point(V, d, st, lane, npos, V.pts + 4 * (par * kRows + lane));
+    const int br = st - lag;
+    if (wave == kWaves - 1 && lane < kRows && br >= 0 && br < nblk)
+      chunk_reduce<WPL>(V, d, V.opart + par * WPL * kRows * 4, w.bout, br, lane, npos);
+  };
+  for (int s = 0; s < nsteps; s += 2) {
+    // the lane indices pass through an empty asm each step, so the compiler
+    // recomputes the lane's LDS addresses inside the step (a few adds)
+    // instead of keeping a dozen of them live across the loop
+    int hv = h, nv = nl;
+    asm volatile("" : "+v"(hv), "+v"(nv));
+    edges(s, 0);
+    pipeline_step<P, H, NHH, OWN, 0, MFIRST, MB>(V, w, wave, gw, hv, nv, scale_own, wreg, acc);
+    __syncthreads();
+    asm volatile("" : "+v"(hv), "+v"(nv));
+    edges(s + 1, 1);
+    pipeline_step<P, H, NHH, OWN, 1, MFIRST, MB>(V, w, wave, gw, hv, nv, scale_own, wreg, acc);
+    __syncthreads();
+  }
 }
 
 template <int P, int H, int NHH>
 __global__ __launch_bounds__(kThreads, 1) void k_fused(FusedBatch batch, DeviceWeights w, int Tm, int Gm,
                                                         int max_tiles) {
   using PT = PrecTraits<P>;
-  constexpr int MW = H / kWaves;    // neurons per wave
-  constexpr int MB = MW / 16;       // 16-neuron blocks per wave
-  constexpr int KS = H / 32;        // K-steps of 32
-  constexpr int NB = kRows / 16;    // 16-row blocks per chunk
-  constexpr int NS = PT::splits;
-  constexpr int STB = act_stride_bf16<H>();
-  constexpr int ST8 = act_stride_fp8<H>();
+  constexpr int WPL = kWaves / NHH;   // waves per hidden layer
+  constexpr int MB = H / WPL / 16;    // 16-neuron blocks per wave
+  constexpr int KS = H / 32;          // K-steps of 32
   extern __shared__ __align__(16) char lds[];
-  const FusedLds LL = fused_lds<P, H>(Tm, Gm, max_tiles);
-  float* s_w1p = (float*)(lds + LL.w1p);
-  float* s_hb = (float*)(lds + LL.hb);
-  float* s_wo = (float*)(lds + LL.wo);
-  float* s_cf = (float*)(lds + LL.cf);
-  float* s_rt = (float*)(lds + LL.rt);
-  float* s_base = (float*)(lds + LL.base);
-  float* s_los = (float*)(lds + LL.los);
-  float* s_samp = (float*)(lds + LL.samp);
-  float* s_dp = (float*)(lds + LL.dp);
-  float* s_hinge = (float*)(lds + LL.hinge);
-  float* s_pts = (float*)(lds + LL.pts);
-  float* s_opart = (float*)(lds + LL.opart);
-  float* s_jl = (float*)(lds + LL.jl);
-  double* s_wt = (double*)(lds + LL.wt);
-  double* s_fac = (double*)(lds + LL.fac);
-  int* s_misc = (int*)(lds + LL.misc);
-
+  const Views V = make_views<P, H, NHH>(lds, Tm, Gm, max_tiles);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int h = lane >> 4, nl = lane & 15;
+  const int own = wave / WPL, gw = wave % WPL;
 
-  // ---- weights of this wave's neurons, resident in VGPRs for the whole kernel
-  using Frag = typename std::conditional<PT::fp8, long, bf16x8>::type;
-  Frag wreg[NHH][MB][KS];
-  float wsc[NHH];
+  // ---- weights of the owned neurons, resident in VGPRs for the whole kernel
+  FragT<P> wreg[MB][KS];
 #pragma unroll
-  for (int l = 0; l < NHH; ++l) {
+  for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-    for (int mb = 0; mb < MB; ++mb) {
-#pragma unroll
-      for (int ks = 0; ks < KS; ++ks) {
-        const size_t fi = frag_index<H>(l, wave, mb, ks, lane);
-        if constexpr (PT::fp8) wreg[l][mb][ks] = ((const long*)w.hidden_lp)[fi];
-        else wreg[l][mb][ks] = __builtin_bit_cast(bf16x8, ((const uint4*)w.hidden_lp)[fi]);
-      }
+    for (int ks = 0; ks < KS; ++ks) {
+      const size_t fi = frag_index<H>(own, gw * MB + mb, ks, lane);
+      if constexpr (PT::fp8) wreg[mb][ks] = ((const long*)w.hidden_lp)[fi];
+      else wreg[mb][ks] = __builtin_bit_cast(bf16x8, ((const uint4*)w.hidden_lp)[fi]);
     }
-    wsc[l] = PT::fp8 ? w.w_scale[l] * w.a_scale[l] : 1.0f;
-  }
-  for (int i = tid; i < 4 * H; i += kThreads) s_w1p[i] = w.w1p[i];
-  for (int i = tid; i < NHH * H; i += kThreads) s_hb[i] = w.hbias[i];
-  for (int i = tid; i < H; i += kThreads) s_wo[i] = w.wout[i];
-
-  // Write this lane's 4 consecutive neurons (m0 .. m0+3) of row n to buffer buf.
-  auto put_act = [&](int buf, int n, int m0, const float v[4], int layer_in) {
-    if constexpr (PT::fp8) {
-      // saturate to the largest E4M3 value: the conversion alone turns values
-      // beyond the last rounding interval into NaN (activations are >= 0)
-      const float inv = w.a_inv[layer_in];
-      float q[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) q[i] = fminf(v[i] * inv, 448.0f);
-      uint32_t word = __builtin_amdgcn_cvt_pk_fp8_f32(q[0], q[1], 0, false);
-      word = __builtin_amdgcn_cvt_pk_fp8_f32(q[2], q[3], word, true);
-      *(uint32_t*)(lds + LL.act + ((size_t)buf * kRows + n) * ST8 + m0) = word;
-    } else {
-      float r[4] = {v[0], v[1], v[2], v[3]};
-#pragma unroll
-      for (int s = 0; s < NS; ++s) {
-        uint16_t b[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          b[i] = bf16_bits(r[i]);
-          r[i] = r[i] - bf16_val(b[i]);
-        }
-        uint2 pk;
-        pk.x = (uint32_t)b[0] | ((uint32_t)b[1] << 16);
-        pk.y = (uint32_t)b[2] | ((uint32_t)b[3] << 16);
-        *(uint2*)(lds + LL.act + (((size_t)(buf * NS + s) * kRows + n) * STB + m0) * 2) = pk;
-      }
-    }
-  };
+  const float scale_own = PT::fp8 ? w.w_scale[own] * w.a_scale[own] : 1.0f;
+  for (int i = tid; i < 4 * H; i += kThreads) V.w1p[i] = w.w1p[i];
+  for (int i = tid; i < NHH * H; i += kThreads) V.hb[i] = w.hbias[i];
+  for (int i = tid; i < H; i += kThreads) V.wo[i] = w.wout[i];
 
   while (true) {
     __syncthreads();
-    if (tid == 0) s_misc[0] = (int)atomicAdd(batch.tile_counter, 1u);
+    if (tid == 0) V.misc[0] = (int)atomicAdd(batch.tile_counter, 1u);
     __syncthreads();
-    const int tile = s_misc[0];
+    const int tile = V.misc[0];
     if (tile >= batch.n_tiles) break;
     const int2 tl = batch.tiles[tile];
     const SolveDesc& d = batch.descs[tl.x];
@@ -209,310 +607,129 @@ __global__ __launch_bounds__(kThreads, 1) void k_fused(FusedBatch batch, DeviceW
     const int k0 = tl.y;
     const int Re = min(kTileR, K - k0);
     const uint32_t tick = d.tick_fixed == 0xFFFFFFFFu ? *d.tick_slot : d.tick_fixed;
-
-    // ---- per-solve tables
-    for (int i = tid; i < G * H; i += kThreads) s_cf[i] = d.cfold[i];
-    for (int i = tid; i < 9 * G; i += kThreads) s_rt[i] = d.Rt[i];
-    for (int i = tid; i < 3 * G * (T + 1); i += kThreads) s_base[i] = d.base[i];
-    if (d.Q_vis != 0.0f)
-      for (int i = tid; i < 2 * T; i += kThreads) s_los[i] = d.los[i];
-    // ---- noise (Section IV-A): every (rollout, step) of the tile
-    for (int i = tid; i < Re * T; i += kThreads) {
-      const int kl = i / T, t = i - kl * T;
-      float u[4];
-      sample_control(d, (uint32_t)(k0 + kl), (uint32_t)t, tick, u);
-      *(float4*)(s_samp + 4 * i) = make_float4(u[0], u[1], u[2], u[3]);
-    }
-    __syncthreads();
-    // ---- dynamics: one lane per rollout
-    if (tid < Re) {
-      RolloutState s;
-#pragma unroll
-      for (int i = 0; i < 3; ++i) { s.dp[i] = 0.0f; s.dv[i] = 0.0f; }
-#pragma unroll
-      for (int i = 0; i < 4; ++i) s.q[i] = d.q0[i];
-      float* dpk = s_dp + 3 * tid * (T + 1);
-      dpk[0] = dpk[1] = dpk[2] = 0.0f;
-      float Jc = 0.0f, Jv = 0.0f;
-      for (int t = 0; t < T; ++t) {
-        const float4 uu = *(const float4*)(s_samp + 4 * (tid * T + t));
-        const float u[4] = {uu.x, uu.y, uu.z, uu.w};
-        Jc = fmaf(u[0], u[0], fmaf(u[1], u[1], fmaf(u[2], u[2], fmaf(u[3], u[3], Jc))));
-        if (d.Q_vis != 0.0f) Jv += alignment_term(s.q, s_los[2 * t] - s.dp[0], s_los[2 * t + 1] - s.dp[1]);
-        quad_step(s, u, d.dt, d.inv_mass, d.gravity);
-        dpk[3 * (t + 1) + 0] = s.dp[0];
-        dpk[3 * (t + 1) + 1] = s.dp[1];
-        dpk[3 * (t + 1) + 2] = s.dp[2];
-      }
-      const float Jg = s.dp[0] * s.dp[0] + s.dp[1] * s.dp[1] + s.dp[2] * s.dp[2] +
-                       2.0f * (s.dp[0] * d.fprog[0] + s.dp[1] * d.fprog[1] + s.dp[2] * d.fprog[2]);
-      s_jl[tid] = d.Q_gate * Jg + d.R_u * Jc + d.Q_vis * Jv;
-    }
-    // ---- Gate-SDF decoder over the tile's queries, kRows at a time
-    const int Pc = kRows / G;                    // positions per chunk
+    tile_prologue(V, d, k0, Re, tick, H);
     const int npos = Re * T;
-    const int nchunks = (npos + Pc - 1) / Pc;
-    for (int c = 0; c < nchunks; ++c) {
-      __syncthreads();   // previous chunk done with s_pts / s_opart; dynamics done
-      if (tid < kRows) {
-        const int p = tid / G, g = tid - p * G;
-        const int q = c * Pc + p;
-        float px = 0.0f, py = 0.0f, pz = 0.0f;
-        if (p < Pc && q < npos) {
-          const int kl = q / T, t = q - kl * T;
-          const int tp = t + (int)d.q_off;
-          const float* dpp = s_dp + 3 * (kl * (T + 1) + tp);
-          const float* R = s_rt + 9 * g;
-          const float* b = s_base + 3 * (g * (T + 1) + tp);
-          px = fmaf(R[0], dpp[0], fmaf(R[1], dpp[1], fmaf(R[2], dpp[2], b[0])));
-          py = fmaf(R[3], dpp[0], fmaf(R[4], dpp[1], fmaf(R[5], dpp[2], b[1])));
-          pz = fmaf(R[6], dpp[0], fmaf(R[7], dpp[1], fmaf(R[8], dpp[2], b[2])));
-        }
-        s_pts[4 * tid + 0] = px;
-        s_pts[4 * tid + 1] = py;
-        s_pts[4 * tid + 2] = pz;
-        s_pts[4 * tid + 3] = (float)((p < Pc) ? g : 0);
-      }
-      __syncthreads();
-      // layer 1 on the vector units, computed in the matrix-core output layout
-#pragma unroll
-      for (int mb = 0; mb < MB; ++mb) {
-        const int m0 = wave * MW + 16 * mb + 4 * h;
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-          const int n = 16 * nb + nl;
-          const float4 pt = *(const float4*)(s_pts + 4 * n);
-          const int g = (int)pt.w;
-          float v[4];
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const float4 wv = *(const float4*)(s_w1p + 4 * (m0 + i));
-            const float x = fmaf(wv.x, pt.x, fmaf(wv.y, pt.y, fmaf(wv.z, pt.z, s_cf[g * H + m0 + i])));
-            v[i] = softplus_fast(x);
-          }
-          put_act(0, n, m0, v, 0);
-        }
-      }
-      // hidden H x H layers on the matrix cores
-      float opart[NB];
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) opart[nb] = 0.0f;
-#pragma unroll
-      for (int l = 0; l < NHH; ++l) {
-        __syncthreads();                 // layer input complete in buffer (l & 1)
-        const int src = l & 1;
-        f32x4 acc[MB][NB];
-#pragma unroll
-        for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-          for (int nb = 0; nb < NB; ++nb) {
-            if constexpr (PT::fp8) acc[mb][nb] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-            else acc[mb][nb] = *(const f32x4*)(s_hb + l * H + wave * MW + 16 * mb + 4 * h);
-          }
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-          if constexpr (PT::fp8) {
-            long bfr[NB];
-#pragma unroll
-            for (int nb = 0; nb < NB; ++nb)
-              bfr[nb] = *(const long*)(lds + LL.act + ((size_t)src * kRows + 16 * nb + nl) * ST8 + 32 * ks + 8 * h);
-#pragma unroll
-            for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-              for (int nb = 0; nb < NB; ++nb)
-                acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(wreg[l][mb][ks], bfr[nb], acc[mb][nb], 0, 0, 0);
-          } else {
-            bf16x8 bfr[NS][NB];
-#pragma unroll
-            for (int s = 0; s < NS; ++s)
-#pragma unroll
-              for (int nb = 0; nb < NB; ++nb)
-                bfr[s][nb] = __builtin_bit_cast(
-                    bf16x8, *(const uint4*)(lds + LL.act +
-                                            (((size_t)(src * NS + s) * kRows + 16 * nb + nl) * STB + 32 * ks + 8 * h) * 2));
-#pragma unroll
-            for (int s = 0; s < NS; ++s)
-#pragma unroll
-              for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-                for (int nb = 0; nb < NB; ++nb)
-                  acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wreg[l][mb][ks], bfr[s][nb], acc[mb][nb], 0, 0, 0);
-          }
-        }
-        // epilogue: bias (FP8 scale), softplus; next layer's operand or output dot
-#pragma unroll
-        for (int mb = 0; mb < MB; ++mb) {
-          const int m0 = wave * MW + 16 * mb + 4 * h;
-#pragma unroll
-          for (int nb = 0; nb < NB; ++nb) {
-            float v[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              const float x = PT::fp8 ? fmaf(acc[mb][nb][i], wsc[l], s_hb[l * H + m0 + i]) : acc[mb][nb][i];
-              v[i] = softplus_fast(x);
-            }
-            if (l + 1 < NHH) {
-              put_act(src ^ 1, 16 * nb + nl, m0, v, l + 1);
-            } else {
-#pragma unroll
-              for (int i = 0; i < 4; ++i) opart[nb] = fmaf(s_wo[m0 + i], v[i], opart[nb]);
-            }
-          }
-        }
-      }
-      // output layer: reduce the lane groups holding the same row, then the waves
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) {
-        float v = opart[nb];
-        v += __shfl_xor(v, 16);
-        v += __shfl_xor(v, 32);
-        if (h == 0) s_opart[wave * kRows + 16 * nb + nl] = v;
-      }
-      __syncthreads();
-      if (tid < kRows) {
-        float sv = w.bout;
-        float acc0 = 0.0f;
-#pragma unroll
-        for (int ww = 0; ww < kWaves; ++ww) acc0 += s_opart[ww * kRows + tid];
-        sv += acc0;
-        // max over the gates of each position (rows p G .. p G + G - 1)
-        const int p = tid / G;
-        float best = sv;
-        for (int g = 1; g < G; ++g) {
-          const float o = __shfl(sv, p * G + g, 64);
-          if (p * G + g < kRows) best = fmaxf(best, o);
-        }
-        const int q = c * Pc + p;
-        if (tid == p * G && p < Pc && q < npos) s_hinge[q] = fmaxf(0.0f, d.d_safe - best);
-      }
+    const int nblk = (npos + kRows / G - 1) / (kRows / G);
+    // waves w and w + 4 share a SIMD: the second runs its products first
+    // (with two hidden layers that is the owner of the last one, whose
+    // epilogue needs the fewest registers beside two accumulator sets)
+    const bool mfirst = wave >= kWaves / 2;
+    if (NHH == 1) {
+      if (mfirst) decoder_tile<P, H, NHH, 0, true, MB>(V, d, w, wave, lane, gw, h, nl, scale_own, wreg, npos, nblk);
+      else decoder_tile<P, H, NHH, 0, false, MB>(V, d, w, wave, lane, gw, h, nl, scale_own, wreg, npos, nblk);
+    } else if (own == 0) {
+      decoder_tile<P, H, NHH, 0, false, MB>(V, d, w, wave, lane, gw, h, nl, scale_own, wreg, npos, nblk);
+    } else {
+      decoder_tile<P, H, NHH, NHH - 1, true, MB>(V, d, w, wave, lane, gw, h, nl, scale_own, wreg, npos, nblk);
     }
-    __syncthreads();
-    // ---- per-rollout costs and the tile's FP64 partials
-    if (tid < Re) {
-      float hs = 0.0f;
-      for (int t = 0; t < T; ++t) hs += s_hinge[tid * T + t];
-      const float J = s_jl[tid] + d.Q_sdf * hs;
-      s_jl[kTileR + tid] = J;
-      d.J[k0 + tid] = J;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      double rho = INFINITY;
-      for (int k = 0; k < Re; ++k) {
-        const float J = s_jl[kTileR + k];
-        if (isfinite(J)) rho = fmin(rho, (double)J);
-      }
-      double eta = 0.0, eta2 = 0.0;
-      for (int k = 0; k < Re; ++k) {
-        const float J = s_jl[kTileR + k];
-        const double wt = (isfinite(J) && isfinite(rho)) ? exp(-((double)J - rho) * d.inv_lambda) : 0.0;
-        s_wt[k] = wt;
-        eta += wt;
-        eta2 += wt * wt;
-      }
-      s_wt[kTileR] = rho;
-      s_wt[kTileR + 1] = eta;
-      s_wt[kTileR + 2] = eta2;
-    }
-    __syncthreads();
-    const int ti = k0 / d.tile_rollouts;
-    double* part = d.partials + (size_t)ti * kPartStride(T);
-    if (tid < 3) part[tid] = s_wt[kTileR + tid];
-    for (int i = tid; i < 4 * T; i += kThreads) {
-      double sacc = 0.0;
-      for (int k = 0; k < Re; ++k) sacc = fma(s_wt[k], (double)s_samp[4 * (k * T) + i], sacc);
-      part[4 + i] = sacc;
-    }
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) {
-      const uint32_t prev = atomicAdd(d.tiles_done, 1u);
-      s_misc[1] = (prev + 1 == (uint32_t)d.n_tiles) ? 1 : 0;
-    }
-    __syncthreads();
-    if (!s_misc[1]) continue;
-    // ---- last tile of this solve: merge the partials in tile order
-    __threadfence();
-    if (tid == 0) {
-      double rho = INFINITY;
-      for (int i = 0; i < d.n_tiles; ++i) {
-        const double* pi = d.partials + (size_t)i * kPartStride(T);
-        if (pi[1] > 0.0) rho = fmin(rho, pi[0]);
-      }
-      double eta = 0.0, eta2 = 0.0;
-      for (int i = 0; i < d.n_tiles; ++i) {
-        const double* pi = d.partials + (size_t)i * kPartStride(T);
-        if (pi[1] > 0.0) {
-          const double f = exp(-(pi[0] - rho) * d.inv_lambda);
-          eta = fma(pi[1], f, eta);
-          eta2 = fma(pi[2], f * f, eta2);
-        }
-      }
-      s_wt[0] = rho;
-      s_wt[1] = eta;
-      s_wt[2] = eta2;
-      *d.tiles_done = 0u;
-    }
-    __syncthreads();
-    for (int j = tid; j < d.n_tiles; j += kThreads) {
-      const double* pj = d.partials + (size_t)j * kPartStride(T);
-      s_fac[j] = (pj[1] > 0.0 && isfinite(s_wt[0])) ? exp(-(pj[0] - s_wt[0]) * d.inv_lambda) : 0.0;
-    }
-    __syncthreads();
-    const double rho = s_wt[0], eta = s_wt[1], eta2 = s_wt[2];
-    const bool ok = isfinite(rho) && eta > 0.0;
-    double* res = d.result;
-    for (int i = tid; i < 4 * T; i += kThreads) {
-      const int t = i >> 2, ch = i & 3;
-      double U;
-      if (ok) {
-        double sacc = 0.0;
-        for (int j = 0; j < d.n_tiles; ++j)
-          sacc = fma(d.partials[(size_t)j * kPartStride(T) + 4 + i], s_fac[j], sacc);
-        U = sacc / eta;
-      } else {
-        const int tt = t < d.U_len ? t : d.U_len - 1;
-        U = d.U_src ? d.U_src[tt * 4 + ch] : d.hover[ch];
-      }
-      res[i] = U;
-      if (t == 0) res[4 * T + RES_U0 + ch] = U;
-      if (ok && d.U_resident && !(d.flags & 1)) {
-        if (t >= 1) d.U_resident[(t - 1) * 4 + ch] = U;
-        if (t == T - 1) d.U_resident[t * 4 + ch] = U;
-      }
-    }
-    if (d.wn)
-      for (int k = tid; k < K; k += kThreads) {
-        const float J = d.J[k];
-        d.wn[k] = (ok && isfinite(J)) ? exp(-((double)J - rho) * d.inv_lambda) / eta : 0.0;
-      }
-    if (tid == 0) {
-      double* r = res + 4 * T;
-      r[RES_TICK] = (double)tick;
-      if (ok) {
-        const double jmin = rho + d.C0;
-        r[RES_STATUS] = 0.0;
-        r[RES_JMIN] = jmin;
-        r[RES_LOGETA] = log(eta) - jmin * d.inv_lambda;
-        r[RES_ESS] = eta * eta / eta2;
-        r[RES_ETA] = eta;
-      } else {
-        r[RES_STATUS] = -5.0;
-        r[RES_JMIN] = NAN;
-        r[RES_LOGETA] = NAN;
-        r[RES_ESS] = 0.0;
-        r[RES_ETA] = 0.0;
-      }
-      if (d.tick_slot) *d.tick_slot = tick + 1u;
-    }
+    tile_epilogue(V, d, k0, Re, tick);
   }
 }
 
-// Zero the batch's work counter and every solve's tile counter.
-__global__ void k_fused_prep(FusedBatch b, int n_solves) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i == 0) *b.tile_counter = 0u;
-  if (i < n_solves) *b.descs[i].tiles_done = 0u;
+// Zero the batch's work counter.
+__global__ void k_fused_prep(FusedBatch b) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *b.tile_counter = 0u;
+}
+
+constexpr int kMergeThreads = 256;
+
+// Merge of one solve's tile partials (workgroup = solve; runs after the fused
+// kernel, whose completion makes every partial visible):
+//   rho = min_i rho_i, f_i = exp(-(rho_i - rho) / lambda),
+//   eta = sum_i eta_i f_i, U*[t][c] = sum_i S_i[t][c] f_i / eta,
+// then the normalised weights, the warm start, the tick and the scalars.
+// Every sum runs in an order fixed by the tile index, so the result does not
+// depend on which workgroup ran which tile or on what else was in the batch.
+__global__ __launch_bounds__(kMergeThreads) void k_fused_merge(FusedBatch batch) {
+  extern __shared__ __align__(16) char lds[];
+  constexpr int NW = kMergeThreads / 64;
+  double* red = (double*)lds;          // 3 NW per-wave partial results
+  double* fac = red + 3 * NW;          // n tile factors
+  const SolveDesc& d = batch.descs[blockIdx.x];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int n = d.n_tiles, T = d.T, K = d.K;
+  const uint32_t tick = d.tick_fixed == 0xFFFFFFFFu ? *d.tick_slot : d.tick_fixed;
+  // rho = min over tiles with weight (min is exact in any order)
+  double r = INFINITY;
+  for (int j = tid; j < n; j += kMergeThreads) {
+    const double* pj = d.partials + (size_t)j * kPartStride(T);
+    if (pj[1] > 0.0) r = fmin(r, pj[0]);
+  }
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) r = fmin(r, __shfl_xor(r, m, 64));
+  if (lane == 0) red[wave] = r;
+  __syncthreads();
+  double rho = red[0];
+#pragma unroll
+  for (int w = 1; w < NW; ++w) rho = fmin(rho, red[w]);
+  // tile factors, and eta, eta2 by a fixed tree
+  double e = 0.0, e2 = 0.0;
+  for (int j = tid; j < n; j += kMergeThreads) {
+    const double* pj = d.partials + (size_t)j * kPartStride(T);
+    const double f = (pj[1] > 0.0 && isfinite(rho)) ? exp(-(pj[0] - rho) * d.inv_lambda) : 0.0;
+    fac[j] = f;
+    e += pj[1] * f;
+    e2 += pj[2] * f * f;
+  }
+  e = wave_sum(e);
+  e2 = wave_sum(e2);
+  if (lane == 0) {
+    red[NW + wave] = e;
+    red[2 * NW + wave] = e2;
+  }
+  __syncthreads();
+  double eta = 0.0, eta2 = 0.0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    eta += red[NW + w];
+    eta2 += red[2 * NW + w];
+  }
+  const bool ok = isfinite(rho) && eta > 0.0;
+  double* res = d.result;
+  // U*[t][c]: one thread per output, tiles in index order
+  for (int i = tid; i < 4 * T; i += kMergeThreads) {
+    const int t = i >> 2, ch = i & 3;
+    double U;
+    if (ok) {
+      double sacc = 0.0;
+#pragma unroll 8
+      for (int j = 0; j < n; ++j) sacc = fma(d.partials[(size_t)j * kPartStride(T) + 4 + i], fac[j], sacc);
+      U = sacc / eta;
+    } else {
+      const int tt = t < d.U_len ? t : d.U_len - 1;
+      U = d.U_src ? d.U_src[tt * 4 + ch] : d.hover[ch];
+    }
+    res[i] = U;
+    if (t == 0) res[4 * T + RES_U0 + ch] = U;
+    if (ok && d.U_resident && !(d.flags & 1)) {
+      if (t >= 1) d.U_resident[(t - 1) * 4 + ch] = U;
+      if (t == T - 1) d.U_resident[t * 4 + ch] = U;
+    }
+  }
+  if (d.wn)
+    for (int k = tid; k < K; k += kMergeThreads) {
+      const float J = d.J[k];
+      d.wn[k] = (ok && isfinite(J)) ? exp(-((double)J - rho) * d.inv_lambda) / eta : 0.0;
+    }
+  if (tid == 0) {
+    double* rr = res + 4 * T;
+    rr[RES_TICK] = (double)tick;
+    if (ok) {
+      const double jmin = rho + d.C0;
+      rr[RES_STATUS] = 0.0;
+      rr[RES_JMIN] = jmin;
+      rr[RES_LOGETA] = log(eta) - jmin * d.inv_lambda;
+      rr[RES_ESS] = eta * eta / eta2;
+      rr[RES_ETA] = eta;
+    } else {
+      rr[RES_STATUS] = -5.0;
+      rr[RES_JMIN] = NAN;
+      rr[RES_LOGETA] = NAN;
+      rr[RES_ESS] = 0.0;
+      rr[RES_ETA] = 0.0;
+    }
+    if (d.tick_slot) *d.tick_slot = tick + 1u;
+  }
 }
 
 // ------------------------------------------------------------------ host side
@@ -520,19 +737,27 @@ __global__ void k_fused_prep(FusedBatch b, int n_solves) {
 template <int P, int H, int NHH>
 static hipError_t launch_fused_t(const FusedBatch& b, const DeviceWeights& w, int Tm, int Gm,
                                  int max_tiles, hipStream_t s) {
-  const FusedLds L = fused_lds<P, H>(Tm, Gm, max_tiles);
-  static int max_set = 0;
-  if ((int)L.total > max_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_fused<P, H, NHH>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.total);
-    if (e != hipSuccess) return e;
-    max_set = (int)L.total;
+  const FusedLds L = fused_lds<P, H, NHH>(Tm, Gm, max_tiles);
+  {
+    // raise the kernel's dynamic LDS limit to the largest size launched so far
+    // (engines on several threads may launch the same instantiation)
+    static std::mutex mu;
+    static int max_set = 0;
+    std::lock_guard<std::mutex> lock(mu);
+    if ((int)L.total > max_set) {
+      hipError_t e = hipFuncSetAttribute((const void*)k_fused<P, H, NHH>,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.total);
+      if (e != hipSuccess) return e;
+      max_set = (int)L.total;
+    }
   }
   int dev = 0, ncu = 0;
-  hipGetDevice(&dev);
-  hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
   const int grid = std::max(1, std::min(b.n_tiles, ncu));
-  hipLaunchKernelGGL((k_fused<P, H, NHH>), dim3(grid), dim3(kThreads), L.total, s, b, w, Tm, Gm, max_tiles);
+  hipLaunchKernelGGL((k_fused<P, H, NHH>), dim3(grid), dim3(kThreads), L.total, s, b, w, Tm,
+                     Gm, max_tiles);
   return hipGetLastError();
 }
 
@@ -549,10 +774,10 @@ static hipError_t launch_fused_p(const FusedBatch& b, const DeviceWeights& w, in
 
 hipError_t launch_fused(const FusedBatch& b, int n_solves, const DeviceWeights& w, int max_T, int max_G,
                         int max_tiles, hipStream_t s, hipEvent_t begin, hipEvent_t end) {
-  hipLaunchKernelGGL(k_fused_prep, dim3((n_solves + 255) / 256), dim3(256), 0, s, b, n_solves);
+  hipLaunchKernelGGL(k_fused_prep, dim3(1), dim3(64), 0, s, b);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if (begin) hipEventRecord(begin, s);
+  if (begin && (e = hipEventRecord(begin, s)) != hipSuccess) return e;
   switch (w.precision) {
     case P_BF16: e = launch_fused_p<P_BF16>(b, w, max_T, max_G, max_tiles, s); break;
     case P_BF16X2: e = launch_fused_p<P_BF16X2>(b, w, max_T, max_G, max_tiles, s); break;
@@ -561,8 +786,10 @@ hipError_t launch_fused(const FusedBatch& b, int n_solves, const DeviceWeights& 
     default: return hipErrorInvalidValue;
   }
   if (e != hipSuccess) return e;
-  if (end) hipEventRecord(end, s);
-  return hipSuccess;
+  if (end && (e = hipEventRecord(end, s)) != hipSuccess) return e;
+  const size_t merge_lds = sizeof(double) * (3 * (kMergeThreads / 64) + (size_t)max_tiles);
+  hipLaunchKernelGGL(k_fused_merge, dim3(n_solves), dim3(kMergeThreads), merge_lds, s, b);
+  return hipGetLastError();
 }
 
 int fused_tile_rollouts(int, int, int) { return kTileR; }
@@ -572,10 +799,12 @@ bool fused_supported(int precision, int H, int n_hidden) {
   return (H == 128 || H == 256) && (n_hidden == 2 || n_hidden == 3);
 }
 
-size_t fused_lds_bytes(int precision, int H, int Tm, int Gm, int max_tiles) {
+size_t fused_lds_bytes(int precision, int H, int n_hidden, int Tm, int Gm, int max_tiles) {
   auto pick = [&](auto p_tag) -> size_t {
     constexpr int P = decltype(p_tag)::value;
-    return H == 128 ? fused_lds<P, 128>(Tm, Gm, max_tiles).total : fused_lds<P, 256>(Tm, Gm, max_tiles).total;
+    if (n_hidden == 2)
+      return H == 128 ? fused_lds<P, 128, 1>(Tm, Gm, max_tiles).total : fused_lds<P, 256, 1>(Tm, Gm, max_tiles).total;
+    return H == 128 ? fused_lds<P, 128, 2>(Tm, Gm, max_tiles).total : fused_lds<P, 256, 2>(Tm, Gm, max_tiles).total;
   };
   switch (precision) {
     case P_BF16: return pick(std::integral_constant<int, P_BF16>{});
@@ -621,10 +850,10 @@ int pack_lowp_weights(int precision, int H, int n_hidden, const mppi_sdf_weights
                       std::vector<float>& a_scale, std::vector<float>& a_inv) {
   if (!fused_supported(precision, H, n_hidden)) return MPPI_EINVAL;
   const int nhh = n_hidden - 1;
-  const int MB = H / kWaves / 16, KS = H / 32;
+  const int NB = H / 16, KS = H / 32;
   const bool fp8 = precision == P_FP8;
   const size_t esz = fp8 ? 8 : 16;
-  blob.assign((size_t)nhh * kWaves * MB * KS * 64 * esz, 0);
+  blob.assign((size_t)nhh * NB * KS * 64 * esz, 0);
   w_scale.assign(nhh, 1.0f);
   a_scale.assign(nhh, 1.0f);
   a_inv.assign(nhh, 1.0f);
@@ -641,23 +870,24 @@ int pack_lowp_weights(int precision, int H, int n_hidden, const mppi_sdf_weights
       a_scale[l] = as;
       a_inv[l] = 1.0f / as;
     }
-    for (int wv = 0; wv < kWaves; ++wv)
-      for (int mb = 0; mb < MB; ++mb)
-        for (int ks = 0; ks < KS; ++ks)
-          for (int lane = 0; lane < 64; ++lane) {
-            const int m = wv * (H / kWaves) + 16 * mb + lane % 16;
-            const size_t fi = ((((size_t)l * kWaves + wv) * MB + mb) * KS + ks) * 64 + lane;
-            for (int j = 0; j < 8; ++j) {
-              const int k = 32 * ks + 8 * (lane / 16) + j;
-              const float v = W[(size_t)m * H + k];
-              if (fp8) {
-                blob[fi * 8 + j] = host_e4m3(v / scale);
-              } else {
-                const uint16_t b = host_bf16_rne(v);
-                memcpy(&blob[fi * 16 + 2 * j], &b, 2);
-              }
+    // fragment (l, nb, ks, lane) at (((l NB + nb) KS + ks) 64 + lane), as
+    // frag_index<H> lays it out
+    for (int nb = 0; nb < NB; ++nb)
+      for (int ks = 0; ks < KS; ++ks)
+        for (int lane = 0; lane < 64; ++lane) {
+          const int m = 16 * nb + lane % 16;
+          const size_t fi = (((size_t)l * NB + nb) * KS + ks) * 64 + lane;
+          for (int j = 0; j < 8; ++j) {
+            const int k = 32 * ks + 8 * (lane / 16) + j;
+            const float v = W[(size_t)m * H + k];
+            if (fp8) {
+              blob[fi * 8 + j] = host_e4m3(v / scale);
+            } else {
+              const uint16_t b = host_bf16_rne(v);
+              memcpy(&blob[fi * 16 + 2 * j], &b, 2);
             }
           }
+        }
   }
   return MPPI_OK;
 }

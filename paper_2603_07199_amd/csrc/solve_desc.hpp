@@ -62,7 +62,6 @@ struct SolveDesc {
   double* result;        // [4T + RES_SCALARS]
   // fused path
   double* partials;      // per tile: rho, eta, S[T][4]
-  uint32_t* tiles_done;  // per-solve completion counter
   int32_t tile_rollouts; // rollouts per fused tile
   int32_t n_tiles;
 };

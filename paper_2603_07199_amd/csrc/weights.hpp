@@ -20,7 +20,7 @@ struct DeviceWeights {
   float bout;
   // FP32: per hidden layer, fragments [mb][ks][64] of W[16 mb + lane%16][4 ks + lane/16]
   const float* hidden_f32;
-  // BF16 family / FP8: per hidden layer, per wave slice, see kernels_mfma.hip
+  // BF16 family / FP8: per hidden layer, fragments [16-neuron block][K-step][64 lanes] (kernels_fused.hip)
   const void* hidden_lp;
   const float* w_scale;  // FP8: per hidden layer weight scale
   const float* a_scale;  // FP8: per hidden layer activation scale
