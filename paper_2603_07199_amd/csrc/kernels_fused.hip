@@ -21,13 +21,14 @@
 // H/8 of its neurons; with two, waves 0-3 own H/4 neurons each of the first
 // and waves 4-7 of the second.  Blocks of 16 rows flow through a software
 // pipeline; in step s
-//   wave 0          gate-frame points of block s
-//   every wave      layer 1 (vector units) of block s-1, H/8 neurons each
+//   wave 1          gate-frame points of block s
+//   every wave      layer 1 of block s-1, H/8 neurons each (FP32 matrix-core
+//                   product with the point, then softplus)
 //   owners of l     matrix-core products of layer l on block s-2-2l into one
 //                   of two register accumulator sets, and the activation
 //                   epilogue (softplus, bf16 split / output dot) of block
 //                   s-3-2l from the other set
-//   last wave       output sum, max over gates and hinge of block s-2-2L
+//   wave 2          output sum, max over gates and hinge of block s-2-2L
 //                   (L hidden H x H layers)
 // with one workgroup barrier per step.  A wave's products and its epilogue
 // work on different blocks, so the matrix cores and the vector units overlap
@@ -232,53 +233,70 @@ __device__ __forceinline__ void put_act(char* buf, uint32_t off, const float v[4
 template <int P>
 using FragT = typename std::conditional<PrecTraits<P>::fp8, long, bf16x8>::type;
 
-// Gate-frame point of row `row` of block c (kRows / G positions per block).
-__device__ __forceinline__ void chunk_point(const Views& V, const SolveDesc& d, int c, int row, int npos,
-                                            float* out4) {
-  const int G = d.G, T = d.T;
-  const int Pc = kRows / G;
-  const int p = row / G, g = row - p * G;
-  const int q = c * Pc + p;
+// Per-tile constants of the decoder's edge work (points and output
+// reduction), read once per tile: the loop's scheduling fences would
+// otherwise make every step reload them from the descriptor.  A block holds
+// kRows / G positions of G gate rows each; this lane's row is position p,
+// gate g of the block.
+struct EdgeConsts {
+  int G, T, Pc, qoff, npos, p, g;
+  float invT, dsafe, bout;
+};
+
+__device__ __forceinline__ EdgeConsts edge_consts(const SolveDesc& d, int lane, int npos, float bout) {
+  EdgeConsts e;
+  e.G = d.G;
+  e.T = d.T;
+  e.Pc = kRows / e.G;
+  e.qoff = (int)d.q_off;
+  e.npos = npos;
+  e.p = lane / e.G;
+  e.g = lane - e.p * e.G;
+  e.invT = 1.0f / (float)e.T;
+  e.dsafe = d.d_safe;
+  e.bout = bout;
+  return e;
+}
+
+// Gate-frame point of this lane's row of block c (lanes 0 .. kRows-1).
+__device__ __forceinline__ void chunk_point(const Views& V, const EdgeConsts& e, int c, float* out4) {
+  const int q = c * e.Pc + e.p;
   float px = 0.0f, py = 0.0f, pz = 0.0f;
-  if (p < Pc && q < npos) {
-    const int kl = q / T, t = q - kl * T;
-    const int tp = t + (int)d.q_off;
-    const float* dpp = V.dp + 3 * (kl * (T + 1) + tp);
-    const float* R = V.rt + 9 * g;
-    const float* b = V.base + 3 * (g * (T + 1) + tp);
+  if (e.p < e.Pc && q < e.npos) {
+    // q = kl T + t; (q + 1/2) / T is at least 1/(2T) away from an integer,
+    // far more than the float error for q < 2^11
+    const int kl = (int)(((float)q + 0.5f) * e.invT), t = q - kl * e.T;
+    const int tp = t + e.qoff;
+    const float* dpp = V.dp + 3 * (kl * (e.T + 1) + tp);
+    const float* R = V.rt + 9 * e.g;
+    const float* b = V.base + 3 * (e.g * (e.T + 1) + tp);
     px = fmaf(R[0], dpp[0], fmaf(R[1], dpp[1], fmaf(R[2], dpp[2], b[0])));
     py = fmaf(R[3], dpp[0], fmaf(R[4], dpp[1], fmaf(R[5], dpp[2], b[1])));
     pz = fmaf(R[6], dpp[0], fmaf(R[7], dpp[1], fmaf(R[8], dpp[2], b[2])));
   }
-  out4[0] = px;
-  out4[1] = py;
-  out4[2] = pz;
-  out4[3] = (float)((p < Pc) ? g : 0);
+  *(float4*)out4 = make_float4(px, py, pz, (float)((e.p < e.Pc) ? e.g : 0));
 }
 
-// Output of row `row` of block c (called by lanes 0 .. kRows-1 of one wave):
-// sum of the per-lane partials of the last layer's owners, max over each
+// Output of this lane's row of block c (lanes 0 .. kRows-1 of one wave): sum
+// of the per-lane partials of the last layer's owners, max over each
 // position's gates, hinge into the tile's table.
 template <int WPL>
-__device__ __forceinline__ void chunk_reduce(const Views& V, const SolveDesc& d, const float* opart, float bout,
-                                             int c, int row, int npos) {
-  const int G = d.G;
+__device__ __forceinline__ void chunk_reduce(const Views& V, const EdgeConsts& e, const float* opart, int c, int row) {
   float acc = 0.0f;
 #pragma unroll
   for (int w = 0; w < WPL; ++w) {
     const float4 o = *(const float4*)(opart + 4 * (w * kRows + row));
     acc += (o.x + o.y) + (o.z + o.w);
   }
-  const float sv = acc + bout;
-  const int Pc = kRows / G;
-  const int p = row / G;
+  const float sv = acc + e.bout;
+  const int base = e.p * e.G;
   float best = sv;
-  for (int g = 1; g < G; ++g) {
-    const float o = __shfl(sv, p * G + g, 64);
-    if (p * G + g < kRows) best = fmaxf(best, o);
+  for (int g = 1; g < e.G; ++g) {
+    const float o = __shfl(sv, base + g, 64);
+    if (base + g < kRows) best = fmaxf(best, o);
   }
-  const int q = c * Pc + p;
-  if (row == p * G && p < Pc && q < npos) V.hinge[q] = fmaxf(0.0f, d.d_safe - best);
+  const int q = c * e.Pc + e.p;
+  if (e.g == 0 && e.p < e.Pc && q < e.npos) V.hinge[q] = fmaxf(0.0f, e.dsafe - best);
 }
 
 // Clipped control samples of the tile (Section IV-A) into V.samp.
@@ -475,21 +493,21 @@ __device__ __forceinline__ void vector_work(const f32x4 (&acc)[MB], char* out, c
     if (mb & 1) sched_fence();
   }
   if constexpr (OWN + 1 == NHH) opart[(gw * kRows + nl) * 4 + h] = op;
-  const float4 pt = *(const float4*)(pts + 4 * nl);
-  const int g = (int)pt.w;
+  // layer 1 on the matrix cores (FP32 16x16x4): A = W1[:, 0..2] of 16 of this
+  // wave's neurons (fourth column zero), B = the 16 rows' gate-frame points
+  // (x, y, z, gate), C = the folded latent term of each row's gate
+  const float bk = pts[4 * nl + h];
+  const int g = (int)pts[4 * nl + 3];
   const int l0 = wave * L1N + 4 * h;            // first layer-1 neuron of this lane
   const uint32_t loff = act_off<P, H>(nl, l0);
 #pragma unroll
   for (int j = 0; j < L1N / 16; ++j) {
-    // gate-frame point . W1 + folded latent term
     const float4 c4 = *(const float4*)(cf + g * H + l0 + 16 * j);
-    const float cc[4] = {c4.x, c4.y, c4.z, c4.w};
+    f32x4 x = {c4.x, c4.y, c4.z, c4.w};
+    x = __builtin_amdgcn_mfma_f32_16x16x4f32(w1p[4 * (wave * L1N + 16 * j + nl) + h], bk, x, 0, 0, 0);
     float v[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const float4 wv = *(const float4*)(w1p + 4 * (l0 + 16 * j + i));
-      v[i] = softplus_fast(fmaf(wv.x, pt.x, fmaf(wv.y, pt.y, fmaf(wv.z, pt.z, cc[i]))));
-    }
+    for (int i = 0; i < 4; ++i) v[i] = softplus_fast(x[i]);
     put_act<P, H>(l1out, loff + act_off<P, H>(0, 16 * j), v, PT::fp8 ? w.a_inv[0] : 1.0f);
   }
 }
@@ -545,11 +563,14 @@ __device__ __forceinline__ void decoder_tile(const Views& V, const SolveDesc& d,
   for (int p = 0; p < 2; ++p)
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb) acc[p][mb] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  // the edge work goes to two waves that run their vector work first and
+  // have slack at the barrier (the products-first waves do not)
+  const EdgeConsts ec = edge_consts(d, lane, npos, w.bout);
   auto edges = [&](int st, int par) {
-    if (wave == 0 && lane < kRows) chunk_point(V, d, st, lane, npos, V.pts + 4 * (par * kRows + lane));
+    if (wave == 1 && lane < kRows) chunk_point(V, ec, st, V.pts + 4 * (par * kRows + lane));
     const int br = st - lag;
-    if (wave == kWaves - 1 && lane < kRows && br >= 0 && br < nblk)
-      chunk_reduce<WPL>(V, d, V.opart + par * WPL * kRows * 4, w.bout, br, lane, npos);
+    if (wave == 2 && lane < kRows && br >= 0 && br < nblk)
+      chunk_reduce<WPL>(V, ec, V.opart + par * WPL * kRows * 4, br, lane);
   };
   for (int s = 0; s < nsteps; s += 2) {
     // the lane indices pass through an empty asm each step, so the compiler
