@@ -302,7 +302,7 @@ __device__ __forceinline__ void chunk_reduce(const Views& V, const EdgeConsts& e
 // Clipped control samples of the tile (Section IV-A) into V.samp.
 __device__ __forceinline__ void tile_noise(const Views& V, const SolveDesc& d, int k0, int Re, uint32_t tick) {
   const int T = d.T;
-  for (int i = threadIdx.x; i < Re * T; i += kThreads) {
+  for (int i = threadIdx.x; i < Re * T; i += blockDim.x) {
     const int kl = i / T, t = i - kl * T;
     float u[4];
     sample_control(d, (uint32_t)(k0 + kl), (uint32_t)t, tick, u);
@@ -313,11 +313,11 @@ __device__ __forceinline__ void tile_noise(const Views& V, const SolveDesc& d, i
 // Per-tile tables, noise and dynamics (all threads of the workgroup call it).
 __device__ void tile_prologue(const Views& V, const SolveDesc& d, int k0, int Re, uint32_t tick, int H) {
   const int tid = threadIdx.x, T = d.T, G = d.G;
-  for (int i = tid; i < G * H; i += kThreads) V.cf[i] = d.cfold[i];
-  for (int i = tid; i < 9 * G; i += kThreads) V.rt[i] = d.Rt[i];
-  for (int i = tid; i < 3 * G * (T + 1); i += kThreads) V.base[i] = d.base[i];
+  for (int i = tid; i < G * H; i += (int)blockDim.x) V.cf[i] = d.cfold[i];
+  for (int i = tid; i < 9 * G; i += (int)blockDim.x) V.rt[i] = d.Rt[i];
+  for (int i = tid; i < 3 * G * (T + 1); i += (int)blockDim.x) V.base[i] = d.base[i];
   if (d.Q_vis != 0.0f)
-    for (int i = tid; i < 2 * T; i += kThreads) V.los[i] = d.los[i];
+    for (int i = tid; i < 2 * T; i += (int)blockDim.x) V.los[i] = d.los[i];
   tile_noise(V, d, k0, Re, tick);
   __syncthreads();
   // dynamics: one lane per rollout
@@ -363,12 +363,13 @@ __device__ void tile_epilogue(const Views& V, const SolveDesc& d, int k0, int Re
   // the decoder reused the samples' space: draw them again (same counters)
   tile_noise(V, d, k0, Re, tick);
   {
-    // hinge sum of rollout k over its T steps: 32 lanes per rollout
-    const int k = tid >> 5, part = tid & 31;
+    // hinge sum of rollout k over its T steps: blockDim / 16 (16 or 32)
+    // lanes per rollout, fixed butterfly
+    const int lpr = blockDim.x / kTileR;
+    const int k = tid / lpr, part = tid - k * lpr;
     float hs = 0.0f;
-    for (int t = part; t < T; t += 32) hs += V.hinge[k * T + t];
-#pragma unroll
-    for (int m = 16; m >= 1; m >>= 1) hs += __shfl_xor(hs, m, 64);
+    for (int t = part; t < T; t += lpr) hs += V.hinge[k * T + t];
+    for (int m = lpr / 2; m >= 1; m >>= 1) hs += __shfl_xor(hs, m, 64);
     if (part == 0 && k < Re) {
       const float J = V.jl[k] + d.Q_sdf * hs;
       V.jl[kTileR + k] = J;
@@ -399,7 +400,7 @@ __device__ void tile_epilogue(const Views& V, const SolveDesc& d, int k0, int Re
   __syncthreads();
   double* part = d.partials + (size_t)(k0 / d.tile_rollouts) * kPartStride(T);
   if (tid < 3) part[tid] = V.wt[kTileR + tid];
-  for (int i = tid; i < 4 * T; i += kThreads) {
+  for (int i = tid; i < 4 * T; i += (int)blockDim.x) {
     double sacc = 0.0;
     for (int k = 0; k < Re; ++k) sacc = fma(V.wt[k], (double)V.samp[4 * (k * T) + i], sacc);
     part[4 + i] = sacc;
