@@ -120,7 +120,7 @@ __host__ __device__ FusedLds fused_lds(int Tm, int Gm, int max_tiles) {
   L.w1p = take(sizeof(float) * 4 * H);
   L.hb = take(sizeof(float) * NHH * H);
   L.wo = take(sizeof(float) * H);
-  L.pts = take(sizeof(float) * 4 * kRows * 2);
+  L.pts = take(sizeof(float) * 4 * kRows * 3);
   L.opart = take(sizeof(float) * 2 * WPL * kRows * 4);
   L.jl = take(sizeof(float) * 2 * kTileR);
   L.wt = take(sizeof(double) * (kTileR + 4));
@@ -465,17 +465,43 @@ __device__ __forceinline__ void products(const char* in, uint32_t boff, const fl
   }
 }
 
+// Layer 1: FP32 16x16x4 matrix-core products (A = W1[:, 0..2] of 16 neurons
+// with a zero fourth column, B = the 16 rows' gate-frame points (x, y, z,
+// gate), C = the folded latent term of each row's gate), then softplus.  The
+// H/16 neuron blocks are split between the waves so that the two phases of a
+// SIMD's pair of waves take about equally long: a products-first wave takes
+// kL1B blocks (its products join the end of its matrix-core phase), a
+// vector-first wave kL1A blocks (products at the start of its vector phase).
+template <int H> struct L1Split {
+  static constexpr int B = H >= 256 ? 3 : 1;               // blocks per products-first wave
+  static constexpr int A = (H / 16 - (kWaves / 2) * B) / (kWaves / 2);
+  static_assert(A >= 0 && (kWaves / 2) * (A + B) * 16 == H, "layer-1 split");
+  // first block of wave w (waves 4-7 products first, 0-3 vector first)
+  __device__ static int first(int wave) { return wave >= kWaves / 2 ? (wave - kWaves / 2) * B : (kWaves / 2) * B + wave * A; }
+};
+
+template <int H, int NB>
+__device__ __forceinline__ void layer1_products(const float* pts, const float* cf, const float* w1p, int b0, int h,
+                                                int nl, f32x4 (&x)[NB > 0 ? NB : 1]) {
+  const float bk = pts[4 * nl + h];
+  const int g = (int)pts[4 * nl + 3];
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    const float4 c4 = *(const float4*)(cf + g * H + 16 * (b0 + j) + 4 * h);
+    x[j] = f32x4{c4.x, c4.y, c4.z, c4.w};
+    x[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(w1p[4 * (16 * (b0 + j) + nl) + h], bk, x[j], 0, 0, 0);
+  }
+}
+
 // Vector part of a step: the epilogue of the owned layer from acc (softplus,
 // then the next layer's operand in `out`, or for the last layer this lane's
-// share of the output dot in `opart`), and layer 1 for this wave's neurons of
-// the block whose gate-frame points are `pts`, into `l1out`.
-template <int P, int H, int NHH, int OWN, int MB>
-__device__ __forceinline__ void vector_work(const f32x4 (&acc)[MB], char* out, char* l1out, float* opart,
-                                            const float* pts, const float* cf, const float* w1p, const float* hb,
-                                            const float* wo, const DeviceWeights& w, int wave, int gw, int h,
-                                            int nl, float scale_own) {
+// share of the output dot in `opart`), and softplus and operand of the
+// wave's NB layer-1 blocks x (first block b0) into `l1out`.
+template <int P, int H, int NHH, int OWN, int MB, int NB>
+__device__ __forceinline__ void vector_work(const f32x4 (&acc)[MB], const f32x4 (&x)[NB > 0 ? NB : 1], char* out,
+                                            char* l1out, float* opart, const float* hb, const float* wo,
+                                            const DeviceWeights& w, int b0, int gw, int h, int nl, float scale_own) {
   using PT = PrecTraits<P>;
-  constexpr int L1N = H / kWaves;   // layer-1 neurons per wave
   const int e0 = 16 * gw * MB + 4 * h;          // first owned neuron of this lane
   const uint32_t eoff = act_off<P, H>(nl, e0);
   float op = 0.0f;
@@ -494,22 +520,14 @@ __device__ __forceinline__ void vector_work(const f32x4 (&acc)[MB], char* out, c
     if (mb & 1) sched_fence();
   }
   if constexpr (OWN + 1 == NHH) opart[(gw * kRows + nl) * 4 + h] = op;
-  // layer 1 on the matrix cores (FP32 16x16x4): A = W1[:, 0..2] of 16 of this
-  // wave's neurons (fourth column zero), B = the 16 rows' gate-frame points
-  // (x, y, z, gate), C = the folded latent term of each row's gate
-  const float bk = pts[4 * nl + h];
-  const int g = (int)pts[4 * nl + 3];
-  const int l0 = wave * L1N + 4 * h;            // first layer-1 neuron of this lane
-  const uint32_t loff = act_off<P, H>(nl, l0);
+  const uint32_t loff = act_off<P, H>(nl, 16 * b0 + 4 * h);
 #pragma unroll
-  for (int j = 0; j < L1N / 16; ++j) {
-    const float4 c4 = *(const float4*)(cf + g * H + l0 + 16 * j);
-    f32x4 x = {c4.x, c4.y, c4.z, c4.w};
-    x = __builtin_amdgcn_mfma_f32_16x16x4f32(w1p[4 * (wave * L1N + 16 * j + nl) + h], bk, x, 0, 0, 0);
+  for (int j = 0; j < NB; ++j) {
     float v[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) v[i] = softplus_fast(x[i]);
+    for (int i = 0; i < 4; ++i) v[i] = softplus_fast(x[j][i]);
     put_act<P, H>(l1out, loff + act_off<P, H>(0, 16 * j), v, PT::fp8 ? w.a_inv[0] : 1.0f);
+    if (j & 1) sched_fence();
   }
 }
 
@@ -525,27 +543,38 @@ __device__ __forceinline__ void vector_work(const f32x4 (&acc)[MB], char* out, c
 template <int P, int H, int NHH, int OWN, int PAR, bool MFIRST, int MB>
 __device__ __forceinline__ void pipeline_step(const Views& V, const DeviceWeights& w, int wave, int gw, int h,
                                               int nl, float scale_own, const FragT<P> (&wreg)[MB][H / 32],
-                                              f32x4 (&acc)[2][MB]) {
+                                              f32x4 (&acc)[2][MB], const float* pts_prev, const float* pts_cur,
+                                              f32x4 (&x1c)[L1Split<H>::A > 0 ? L1Split<H>::A : 1]) {
   constexpr int WPL = kWaves / NHH;
   constexpr size_t AB = act_buf_bytes<P, H>();
   const char* in = V.act + (2 * OWN + PAR) * AB;
   char* out = V.act + (2 * (OWN + 1 < NHH ? OWN + 1 : 0) + 1 - PAR) * AB;
   char* l1out = V.act + (1 - PAR) * AB;
   float* op = V.opart + (1 - PAR) * WPL * kRows * 4;
-  const float* pts = V.pts + 4 * (1 - PAR) * kRows;
   const uint32_t boff = act_off<P, H>(nl, 8 * h);
   BFragT<P> b0[PrecTraits<P>::splits];
+  const int l1b = L1Split<H>::first(wave);
   if constexpr (MFIRST) {
+    // matrix-core phase: owned layer, then this wave's layer-1 blocks of
+    // block s-1; vector phase after it
+    constexpr int NB = L1Split<H>::B;
+    f32x4 x1[NB > 0 ? NB : 1];
     read_operands<P, H>(in, boff, 0, b0);
     products<P, H, OWN, MB>(in, boff, V.hb, gw, h, wreg, b0, acc[PAR]);
-    vector_work<P, H, NHH, OWN, MB>(acc[1 - PAR], out, l1out, op, pts, V.cf, V.w1p, V.hb, V.wo, w, wave, gw, h, nl,
-                                    scale_own);
+    layer1_products<H, NB>(pts_prev, V.cf, V.w1p, l1b, h, nl, x1);
+    sched_fence();
+    vector_work<P, H, NHH, OWN, MB, NB>(acc[1 - PAR], x1, out, l1out, op, V.hb, V.wo, w, l1b, gw, h, nl, scale_own);
   } else {
+    // vector phase (layer-1 products of block s-1 carried from the previous
+    // step), then the matrix-core phase, which ends with the layer-1
+    // products of block s for the next step: no matrix-core instruction in
+    // the vector phase, where it would queue behind the other wave's products
+    constexpr int NB = L1Split<H>::A;
     read_operands<P, H>(in, boff, 0, b0);
-    vector_work<P, H, NHH, OWN, MB>(acc[1 - PAR], out, l1out, op, pts, V.cf, V.w1p, V.hb, V.wo, w, wave, gw, h, nl,
-                                    scale_own);
+    vector_work<P, H, NHH, OWN, MB, NB>(acc[1 - PAR], x1c, out, l1out, op, V.hb, V.wo, w, l1b, gw, h, nl, scale_own);
     sched_fence();
     products<P, H, OWN, MB>(in, boff, V.hb, gw, h, wreg, b0, acc[PAR]);
+    layer1_products<H, NB>(pts_cur, V.cf, V.w1p, l1b, h, nl, x1c);
   }
 }
 
@@ -564,15 +593,25 @@ __device__ __forceinline__ void decoder_tile(const Views& V, const SolveDesc& d,
   for (int p = 0; p < 2; ++p)
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb) acc[p][mb] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-  // the edge work goes to two waves that run their vector work first and
-  // have slack at the barrier (the products-first waves do not)
+  f32x4 x1c[L1Split<H>::A > 0 ? L1Split<H>::A : 1];
+#pragma unroll
+  for (int j = 0; j < (L1Split<H>::A > 0 ? L1Split<H>::A : 1); ++j) x1c[j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  // Gate-frame points of block b live in slot b % 3: in step s wave 1 writes
+  // block s+1 while the layer-1 products read blocks s-1 and s.  The edge
+  // work goes to two waves that run their vector work first and have slack at
+  // the barrier (the products-first waves do not).
   const EdgeConsts ec = edge_consts(d, lane, npos, w.bout);
+  if (wave == 1 && lane < kRows) chunk_point(V, ec, 0, V.pts + 4 * lane);
+  __syncthreads();
+  int slot = 0;                       // = s % 3
   auto edges = [&](int st, int par) {
-    if (wave == 1 && lane < kRows) chunk_point(V, ec, st, V.pts + 4 * (par * kRows + lane));
+    const int nxt = slot == 2 ? 0 : slot + 1;
+    if (wave == 1 && lane < kRows) chunk_point(V, ec, st + 1, V.pts + 4 * (nxt * kRows + lane));
     const int br = st - lag;
     if (wave == 2 && lane < kRows && br >= 0 && br < nblk)
       chunk_reduce<WPL>(V, ec, V.opart + par * WPL * kRows * 4, br, lane);
   };
+  auto slot_pts = [&](int sl) { return V.pts + 4 * kRows * sl; };
   for (int s = 0; s < nsteps; s += 2) {
     // the lane indices pass through an empty asm each step, so the compiler
     // recomputes the lane's LDS addresses inside the step (a few adds)
@@ -580,12 +619,16 @@ __device__ __forceinline__ void decoder_tile(const Views& V, const SolveDesc& d,
     int hv = h, nv = nl;
     asm volatile("" : "+v"(hv), "+v"(nv));
     edges(s, 0);
-    pipeline_step<P, H, NHH, OWN, 0, MFIRST, MB>(V, w, wave, gw, hv, nv, scale_own, wreg, acc);
+    pipeline_step<P, H, NHH, OWN, 0, MFIRST, MB>(V, w, wave, gw, hv, nv, scale_own, wreg, acc,
+                                                 slot_pts(slot == 0 ? 2 : slot - 1), slot_pts(slot), x1c);
     __syncthreads();
+    slot = slot == 2 ? 0 : slot + 1;
     asm volatile("" : "+v"(hv), "+v"(nv));
     edges(s + 1, 1);
-    pipeline_step<P, H, NHH, OWN, 1, MFIRST, MB>(V, w, wave, gw, hv, nv, scale_own, wreg, acc);
+    pipeline_step<P, H, NHH, OWN, 1, MFIRST, MB>(V, w, wave, gw, hv, nv, scale_own, wreg, acc,
+                                                 slot_pts(slot == 0 ? 2 : slot - 1), slot_pts(slot), x1c);
     __syncthreads();
+    slot = slot == 2 ? 0 : slot + 1;
   }
 }
 
