@@ -272,9 +272,8 @@ int acquire_slot(mppi_engine* e, uint64_t id, int* slot) {
   }
   if ((int)e->inst.size() >= e->cfg.max_instances) return MPPI_EAGAIN;
   const int s = (int)e->inst.size();
-  // a new instance starts from hover with tick 0 (ticks are zeroed at create)
-  HIPCHK(e, hipMemcpy(e->instU + (size_t)s * e->cfg.T_max * 4, e->hover.data(),
-                      sizeof(double) * 4 * e->cfg.T_max, hipMemcpyHostToDevice));
+  // a new instance starts from hover with tick 0: every slot of the table is
+  // filled with hover and tick 0 at create, so no copy is needed here
   e->inst.push_back(InstInfo{id, e->cfg.T_max, false});
   e->inst_map[id] = s;
   *slot = s;
@@ -821,6 +820,13 @@ int mppi_create(const mppi_config* cfg, const mppi_sdf_weights* w, mppi_engine**
   if (hipMemset(e->instTick, 0, sizeof(uint32_t) * nI) != hipSuccess) return bail(MPPI_EDEVICE);
   e->hover.assign((size_t)4 * c.T_max, 0.0);
   for (int t = 0; t < c.T_max; ++t) e->hover[4 * t] = c.mass * c.gravity;
+  {
+    // every instance slot starts at hover
+    std::vector<double> all(e->hover.size() * nI);
+    for (size_t i = 0; i < nI; ++i) memcpy(all.data() + i * e->hover.size(), e->hover.data(), sizeof(double) * e->hover.size());
+    if (hipMemcpy(e->instU, all.data(), sizeof(double) * all.size(), hipMemcpyHostToDevice) != hipSuccess)
+      return bail(MPPI_EDEVICE);
+  }
   const uint64_t budget = c.hbm_budget_bytes ? std::min<uint64_t>(c.hbm_budget_bytes, e->pool_bytes) : e->pool_bytes;
   e->stats.budget = budget;
   e->adm = std::make_unique<Admission>(budget, c.max_inflight, c.queue_depth);
