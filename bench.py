@@ -252,8 +252,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build shards nothing across GPUs "
-              "(see DESIGN.md for how the path would shard); run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU only: the library runs every solve on one GPU "
+              "and shards nothing across GPUs; run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
     from paper_2603_07199_amd import mppi as M
     M.load_library()

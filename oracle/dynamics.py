@@ -1,8 +1,8 @@
 """Quadrotor rollout f(x, u) for MPPI (oracle side), float64.
 
 Section IV-A uses a standard quadrotor model with state [p, v, q, omega].
-The paper's input is four rotor-thrust rates; this build uses the
-collective-thrust + body-rate input of its benchmark configurations.
+The paper's input is four rotor-thrust rates; here the input is collective
+thrust + body rates, the form of the workloads the library is measured on.
 Readings where the paper is silent:
 
 * state layout x = [p(3), q(4) as (w, x, y, z), v(3), omega(3)], world z up;

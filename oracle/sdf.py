@@ -4,7 +4,7 @@
   r(p) = max(|y|, |z|) on the gate plane x = 0, and
   s_guide(p) = c + |x| tan(alpha) - r(p).  The paper leaves c and alpha
   open; with the 1.0 m inner opening of Section V, c = 0.5 m, and
-  tan(alpha) = 0.5 is this build's choice.
+  tan(alpha) = 0.5 is this library's reading.
 * Learned decoder g_phi(z, PE(p)), Section III-B: an MLP on the
   concatenation of the encoded query point and the latent code z.  Reading:
   PE is the identity (input width 3 + 64 = 67), the coordinates occupy input
@@ -13,7 +13,7 @@
   The paper's Fig. 2 duplicates z for every query and concatenates;
   ``mlp_concat`` does exactly that, ``mlp_fold`` applies the first layer's
   latent block once per gate (an exact re-association).
-* Several gates per solve (this build's multi-gate workloads): the field at
+* Several gates per solve (the multi-gate workloads): the field at
   a point is the maximum over gates of each gate's field (union of the safe
   funnels); with one gate this is the paper's single-latent case.
 """
