@@ -53,6 +53,18 @@ def _mfma_flops_per_query(layers):
     return 2.0 * n_hh * H * H
 
 
+# Vector-unit work of the decoder: one softplus per hidden neuron and query
+# (768 at 67-256-256-256-1), 12 lane-slots each (two quarter-rate
+# transcendentals = 8, four full-rate operations).  Peak: 256 CUs x 4 SIMDs x
+# 16 lanes x 2.4 GHz of non-packed float32 issue.
+SOFTPLUS_LANE_SLOTS = 12
+VALU_PEAK_LANE_SLOTS = 256 * 4 * 16 * 2.4e9
+
+
+def _softplus_per_query(layers):
+    return sum(layers[1:-1])
+
+
 def _source_hash(path):
     full = os.path.join(ROOT, "paper_2603_07199_amd", "csrc", KERNEL_SOURCES[path])
     with open(full, "rb") as f:
@@ -284,6 +296,12 @@ def main():
                    "parallelism": "single-gpu"},
         "latency_ms": {"p50": float(np.percentile(main_leg["lat_ms"], 50)),
                        "p99": float(np.percentile(main_leg["lat_ms"], 99))},
+        "roofline_valu": {"bound": "alu",
+                          "achieved": _softplus_per_query(LAYERS) * SOFTPLUS_LANE_SLOTS * queries
+                          / (main_leg["sdf_ms"] * 1e-3),
+                          "peak": VALU_PEAK_LANE_SLOTS, "unit": "lane-slot/s",
+                          "frac": _softplus_per_query(LAYERS) * SOFTPLUS_LANE_SLOTS * queries
+                          / (main_leg["sdf_ms"] * 1e-3) / VALU_PEAK_LANE_SLOTS},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": traffic,
                      "kernel": "k_sdf_f32" if args.path == "plain" else "k_fused",

@@ -128,3 +128,67 @@ def test_fused_ragged_shapes_and_gates():
         say(f"fused ragged K={K} T={T} G={G}: u0 err {e:.2e}")
         assert e <= U0_TOL
     eng.close()
+
+
+def test_fused_alignment_cost_two_hidden_layers():
+    """Perception-alignment cost (eq. 6, Q_vis > 0) through the fused path's
+    dynamics, on the P2 decoder shape at a reduced K."""
+    M = require_gpu()
+    layers = (67, 256, 256, 256, 1)
+    eng, w = _engine(M, layers, "bf16x3", 512, 30, 4, wseed=2, bias=0.2)
+    for seed in (5, 6):
+        prob = sc.make_problem(512, 30, 4, rot="yaw", start="moving", seed=seed, d_safe=1.0, Q_vis=0.5,
+                               instance_id=300 + seed)
+        ref = oracle.solve(prob, w, sc.MODEL, contract="bf16w")
+        out = eng.step(prob)
+        assert out["rc"] == 0
+        e = u0_error(out["u0"], ref["u0"])
+        dJ = np.abs(out["J"] - ref["J"])
+        say(f"fused Q_vis=0.5 seed {seed}: u0 err {e:.2e}, max |dJ| {dJ.max():.2e}")
+        assert e <= U0_TOL
+        assert np.all(dJ <= 2e-5 * (np.abs(ref["J"]) + prob["Q_sdf"] * prob["T"] + 1.0))
+    eng.close()
+
+
+@pytest.mark.parametrize("precision", ["bf16", "fp8"])
+def test_fused_low_precision_two_hidden_layers(precision):
+    """BF16 and FP8 on the two-hidden-layer decoder (the served shape), each
+    against its own contract; reported like the P1 variants."""
+    M = require_gpu()
+    layers = (67, 256, 256, 256, 1)
+    W, b = sc.xavier_weights(layers, seed=3)
+    probs = [sc.make_problem(384, 24, 4, rot="yaw", start="moving", seed=s, d_safe=1.0, instance_id=400 + s)
+             for s in (1, 2, 3)]
+    scales = _act_scales(layers, W, b, probs) if precision == "fp8" else None
+    eng, w = _engine(M, layers, precision, 384, 24, 4, act_scale=scales, wseed=3)
+    errs, jrel = [], []
+    for prob in probs:
+        ref = oracle.solve(prob, w, sc.MODEL, contract=CONTRACT[precision], act_scales=scales)
+        out = eng.step(prob)
+        assert out["rc"] == 0
+        errs.append(u0_error(out["u0"], ref["u0"]))
+        jrel.append(np.abs(out["J"] - ref["J"]) / (np.abs(ref["J"]) + prob["Q_sdf"] * prob["T"] + 1.0))
+    jr = np.concatenate(jrel)
+    say(f"fused {precision} 67-256-256-256-1: u0 err vs {CONTRACT[precision]} max {max(errs):.2e} "
+        f"median {np.median(errs):.2e}; relative cost error p50 {np.percentile(jr, 50):.1e} "
+        f"p90 {np.percentile(jr, 90):.1e}")
+    assert np.median(errs) <= 2e-2
+    assert np.percentile(jr, 90) <= 1e-3
+    eng.close()
+
+
+def test_fused_h128_two_hidden_layers():
+    """H = 128 with two hidden layers (each wave owns 32 neurons of one
+    layer, layer-1 blocks split 1:1)."""
+    M = require_gpu()
+    layers = (67, 128, 128, 128, 1)
+    eng, w = _engine(M, layers, "bf16x3", 600, 25, 3, wseed=5, bias=0.3)
+    for K, T, G in ((600, 25, 3), (33, 7, 1)):
+        prob = sc.make_problem(K, T, G, rot="haar", start="moving", seed=K, d_safe=1.0, instance_id=500 + K)
+        ref = oracle.solve(prob, w, sc.MODEL, contract="bf16w")
+        out = eng.step(prob)
+        assert out["rc"] == 0
+        e = u0_error(out["u0"], ref["u0"])
+        say(f"fused H=128 x2 K={K} T={T} G={G}: u0 err {e:.2e}")
+        assert e <= U0_TOL
+    eng.close()
