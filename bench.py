@@ -65,10 +65,17 @@ def _softplus_per_query(layers):
     return sum(layers[1:-1])
 
 
+KERNEL_HEADERS = ("device_common.hpp", "kernels.hpp", "solve_desc.hpp", "weights.hpp")
+
+
 def _source_hash(path):
-    full = os.path.join(ROOT, "paper_2603_07199_amd", "csrc", KERNEL_SOURCES[path])
-    with open(full, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """sha256 (first 16 hex digits) over the kernel source and the device
+    headers it compiles with, in a fixed order."""
+    h = hashlib.sha256()
+    for name in (KERNEL_SOURCES[path],) + KERNEL_HEADERS:
+        with open(os.path.join(ROOT, "paper_2603_07199_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def _traffic(path, precision, launches_queries):

@@ -172,8 +172,9 @@ def test_fused_low_precision_two_hidden_layers(precision):
     say(f"fused {precision} 67-256-256-256-1: u0 err vs {CONTRACT[precision]} max {max(errs):.2e} "
         f"median {np.median(errs):.2e}; relative cost error p50 {np.percentile(jr, 50):.1e} "
         f"p90 {np.percentile(jr, 90):.1e}")
-    assert np.median(errs) <= 2e-2
-    assert np.percentile(jr, 90) <= 1e-3
+    # observed: median 6.6e-4 (bf16), 2.9e-3 (fp8); cost p90 1.5e-6, 2.4e-5
+    assert np.median(errs) <= {"bf16": 3e-3, "fp8": 1e-2}[precision]
+    assert np.percentile(jr, 90) <= 1e-4
     eng.close()
 
 
