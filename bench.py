@@ -3,6 +3,9 @@
 Workload (one step = one MPPI iteration of every staged request): K = 4096
 rollouts, horizon T = 50 (dt = 0.02 s), 4 gates, Gate-SDF decoder
 67 -> 256 -> 256 -> 256 -> 1, seeded synthetic inputs (see scenarios/).
+With --workload fleet: the large served fleet instead, 1024 instances of
+K = 2048, T = 40, 8 gates, decoder 67 -> 512 -> 512 -> 512 -> 1, one step =
+one control tick of every instance.
 The requests are staged into device memory before timing (mppi_batch_*), so
 the timed region holds kernel launches only; each instance's warm start and
 RNG tick advance on the device from step to step.
@@ -15,7 +18,8 @@ stream through mppi_submit / mppi_poll, with latency probes of the workload's
 shape) and the FP64 oracle timed on the host cores.
 
     python bench.py [--steps K] [--warmup W] [--path fused|plain]
-                    [--precision bf16x3|bf16x2|bf16|fp32] [--batch B]
+                    [--precision bf16x3|bf16x2|bf16|fp8|fp32] [--batch B]
+                    [--workload paper|fleet]
 """
 from __future__ import annotations
 
@@ -37,13 +41,27 @@ import scenarios as sc  # noqa: E402
 
 HBM_PEAK = 8.0e12
 PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "bf16x2": 2500.0, "bf16x3": 2500.0, "fp8": 5000.0}
+# the workload (set by --workload): configuration name, shape, decoder
+WORKLOADS = {"paper": ("P2", 1), "fleet": ("S2", 1024)}   # name, default solves per step
+CFG = "P2"
 LAYERS = (67, 256, 256, 256, 1)
 K_, T_, G_ = 4096, 50, 4
+
+
+def _set_workload(name):
+    global CFG, LAYERS, K_, T_, G_
+    CFG = WORKLOADS[name][0]
+    c = sc.CONFIGS[CFG]
+    LAYERS, K_, T_, G_ = tuple(c["layers"]), c["K"], c["T"], c["G"]
+
+
+def _workload_str():
+    return f"MPPI solve K={K_} T={T_} dt=0.02 G={G_} decoder " + "-".join(str(x) for x in LAYERS)
 KERNEL_SOURCES = {"plain": "kernels_plain.hip", "fused": "kernels_fused.hip"}
 
 
 def _problems(n, M):
-    return [sc.config_problem("P2", 1 + i, instance_id=10_000 + i, tick=M.TICK_RESIDENT)
+    return [sc.config_problem(CFG, 1 + i, instance_id=10_000 + i, tick=M.TICK_RESIDENT)
             for i in range(n)]
 
 
@@ -81,7 +99,7 @@ def _source_hash(path):
 def _traffic(path, precision, launches_queries):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3
     counter summary, or None when absent or taken on a different kernel."""
-    f = os.path.join(ROOT, "profiles", f"traffic_{path}_{precision}_p2.json")
+    f = os.path.join(ROOT, "profiles", f"traffic_{path}_{precision}_{CFG.lower()}.json")
     if not os.path.exists(f):
         return None
     with open(f) as fh:
@@ -92,11 +110,11 @@ def _traffic(path, precision, launches_queries):
 
 
 def run_leg(M, path, precision, batch, steps, warmup):
-    W, b = sc.config_weights("P2")
+    W, b = sc.config_weights(CFG)
     probs = _problems(batch, M)
     eng = M.Engine((W, b), sc.MODEL, K_max=K_, T_max=T_, G_max=G_, hidden=LAYERS[1],
                    n_hidden=len(LAYERS) - 2, precision=precision, path=path,
-                   budget=2 << 30, timing=True, max_instances=max(64, batch))
+                   budget=8 << 30, timing=True, max_instances=max(64, batch))
     bt = eng.batch(probs)
     for _ in range(warmup):
         bt.run()
@@ -220,19 +238,20 @@ def served_leg(M, precision, n_req, plain_subset=64):
 
 
 def cpu_baseline():
-    """The FP64 oracle on one full paper-scale solve (K = 4096, T = 50, G = 4)."""
+    """The FP64 oracle on one full solve of the workload (for the fleet: one
+    instance, one tick)."""
     import torch
 
     import oracle
-    W, b = sc.config_weights("P2")
-    prob = sc.config_problem("P2", 1)
+    W, b = sc.config_weights(CFG)
+    prob = sc.config_problem(CFG, 1)
     t0 = time.perf_counter()
     oracle.solve(prob, (W, b), sc.MODEL)
     dt = time.perf_counter() - t0
     return {"value": K_ * T_ / dt, "unit": "rollout-steps/s", "cores": int(torch.get_num_threads()),
             "kind": "oracle",
             "sample": f"one full solve of the workload (K={K_}, T={T_}, G={G_}, "
-                      f"67-256-256-256-1 decoder) in float64: {dt:.2f} s"}
+                      f"{'-'.join(str(x) for x in LAYERS)} decoder) in float64: {dt:.2f} s"}
 
 
 def _plain_copy(nbytes):
@@ -260,8 +279,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--path", default="fused", choices=["plain", "fused"])
-    ap.add_argument("--precision", default="bf16x3", choices=["fp32", "bf16", "bf16x2", "bf16x3"])
-    ap.add_argument("--batch", type=int, default=1)
+    ap.add_argument("--precision", default="bf16x3", choices=["fp32", "bf16", "bf16x2", "bf16x3", "fp8"])
+    ap.add_argument("--batch", type=int, default=0, help="solves per step (default: 1, fleet: 1024)")
+    ap.add_argument("--workload", default="paper", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
     ap.add_argument("--no-served", action="store_true")
@@ -274,6 +294,12 @@ def main():
         print("bench.py measures one GPU only: the library runs every solve on one GPU "
               "and shards nothing across GPUs; run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
+    _set_workload(args.workload)
+    if args.batch <= 0:
+        args.batch = WORKLOADS[args.workload][1]
+    if args.precision == "fp8":
+        raise SystemExit("bench.py runs the bfloat16 kinds and fp32; FP8 needs activation scales "
+                         "calibrated per network (see the tests)")
     from paper_2603_07199_amd import mppi as M
     M.load_library()
     if args.copy_mib:
@@ -298,7 +324,7 @@ def main():
         "vs_baseline": None,
         "dtype": {"fp32": "f32", "bf16": "bf16", "bf16x2": "bf16x2", "bf16x3": "bf16x3", "fp8": "fp8"}[args.precision],
         "data": "synthetic",
-        "config": {"workload": f"MPPI solve K={K_} T={T_} dt=0.02 G={G_} decoder 67-256-256-256-1",
+        "config": {"workload": _workload_str(),
                    "path": args.path, "precision": args.precision, "solves_per_step": args.batch,
                    "parallelism": "single-gpu"},
         "latency_ms": {"p50": float(np.percentile(main_leg["lat_ms"], 50)),
@@ -311,7 +337,7 @@ def main():
                           / (main_leg["sdf_ms"] * 1e-3) / VALU_PEAK_LANE_SLOTS},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": traffic,
-                     "kernel": "k_sdf_f32" if args.path == "plain" else "k_fused",
+                     "kernel": "k_sdf_f32" if args.path == "plain" else ("k_wide" if LAYERS[1] == 512 else "k_fused"),
                      "kernel_ms": main_leg["sdf_ms"],
                      "algorithmic_flops_per_launch": flops},
     }
@@ -320,7 +346,7 @@ def main():
         out["fp32_plain"] = {"rollout_steps_per_s": ref["rollout_steps_per_s"],
                              "ms_per_step": ref["ms_per_step"],
                              "speedup": main_leg["rollout_steps_per_s"] / ref["rollout_steps_per_s"]}
-    if not args.no_served and args.path == "fused":
+    if not args.no_served and args.path == "fused" and args.workload == "paper":
         out["served"] = served_leg(M, args.precision, args.served_requests)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()

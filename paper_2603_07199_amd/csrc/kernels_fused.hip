@@ -797,6 +797,342 @@ __global__ __launch_bounds__(kMergeThreads) void k_fused_merge(FusedBatch batch)
   }
 }
 
+// ------------------------------------------------------- wide decoder (H = 512)
+//
+// At H = 512 a hidden layer's bfloat16 weights (512 KB) no longer fit in a
+// compute unit, so the decoder streams them: the weights of one K-step of
+// 32 inputs for all H neurons (one "slice", 32 KB in bfloat16, 16 KB in FP8)
+// pass from L2 through a two-slice LDS ring that the workgroup's 4 waves
+// share, one slice per step with one barrier per step, while each wave keeps
+// its own 16 query rows in registers through every layer.  A layer's FP32
+// accumulators of 16 rows x H neurons (128 VGPRs per lane) turn into the next
+// layer's matrix-core operands without leaving the registers: a lane holds
+// neurons 16 nb + 4 (lane / 16) + i of its row in accumulator block nb, and the
+// weights are packed with their input index permuted so that the 8 operand
+// values of K-step ks are exactly the lane's values of accumulator blocks
+// 2 ks and 2 ks + 1 (the product is the same sum in another order).  Layer 1
+// is evaluated K-step by K-step from the row's gate-frame point in the same
+// order.  One wave per SIMD (up to 512 registers): the matrix cores and the
+// vector units overlap inside the wave, the next K-step's operands being
+// formed while the current K-step's products run.
+
+constexpr int kWideWaves = 4;
+constexpr int kWideThreads = 64 * kWideWaves;
+
+template <int P> __host__ __device__ constexpr int frag_bytes() { return PrecTraits<P>::fp8 ? 8 : 16; }
+
+// Bytes of one weight slice: H / 16 fragments of 64 lanes.
+template <int P, int H> __host__ __device__ constexpr int wide_slice_bytes() { return (H / 16) * 64 * frag_bytes<P>(); }
+
+// Input neuron of operand slot j (< 8) of lane group hq (= lane / 16) in
+// K-step ks: the lane's accumulator values of blocks 2 ks and 2 ks + 1.
+__host__ __device__ constexpr int wide_input(int ks, int hq, int j) {
+  return 32 * ks + (j < 4 ? 4 * hq + j : 16 + 4 * hq + (j - 4));
+}
+
+template <int P, int H, int NHH>
+__host__ __device__ FusedLds wide_lds(int Tm, int Gm, int max_tiles) {
+  FusedLds L{};
+  size_t o = 0;
+  auto take = [&](size_t b) { const size_t r = o; o = (o + b + 15) / 16 * 16; return r; };
+  L.act = take(2 * (size_t)wide_slice_bytes<P, H>());     // weight slice ring
+  L.w1p = take(sizeof(float) * 4 * H);
+  L.hb = take(sizeof(float) * NHH * H);
+  L.wo = take(sizeof(float) * H);
+  L.jl = take(sizeof(float) * 2 * kTileR);
+  L.wt = take(sizeof(double) * (kTileR + 4));
+  L.misc = take(64);
+  L.pts = take(sizeof(float) * 4 * kTileR * Tm);          // control samples
+  L.cf = take(sizeof(float) * Gm * H);
+  L.rt = take(sizeof(float) * 9 * Gm);
+  L.base = take(sizeof(float) * 3 * Gm * (Tm + 1));
+  L.los = take(sizeof(float) * 2 * Tm);
+  L.dp = take(sizeof(float) * 3 * kTileR * (Tm + 1));
+  L.hinge = take(sizeof(float) * kTileR * Tm);
+  L.fac = take(sizeof(double) * max_tiles);
+  L.total = o;
+  return L;
+}
+
+template <int P, int H, int NHH>
+__device__ __forceinline__ Views make_wide_views(char* lds, int Tm, int Gm, int max_tiles) {
+  const FusedLds L = wide_lds<P, H, NHH>(Tm, Gm, max_tiles);
+  Views v{};
+  v.act = lds + L.act;
+  v.samp = (float*)(lds + L.pts);
+  v.w1p = (float*)(lds + L.w1p);
+  v.hb = (float*)(lds + L.hb);
+  v.wo = (float*)(lds + L.wo);
+  v.cf = (float*)(lds + L.cf);
+  v.rt = (float*)(lds + L.rt);
+  v.base = (float*)(lds + L.base);
+  v.los = (float*)(lds + L.los);
+  v.dp = (float*)(lds + L.dp);
+  v.hinge = (float*)(lds + L.hinge);
+  v.jl = (float*)(lds + L.jl);
+  v.wt = (double*)(lds + L.wt);
+  v.fac = (double*)(lds + L.fac);
+  v.misc = (int*)(lds + L.misc);
+  return v;
+}
+
+// One slice's share of this thread (16-byte pieces, coalesced), held in
+// native vector registers (a copy through HIP's uint4 struct becomes a
+// memcpy that stays in scratch memory).
+using u32x4 = __attribute__((ext_vector_type(4))) unsigned int;
+template <int P, int H>
+struct SliceCopy {
+  static constexpr int N = wide_slice_bytes<P, H>() / 16 / kWideThreads;
+  static_assert(N * 16 * kWideThreads == wide_slice_bytes<P, H>(), "slice split");
+  u32x4 r[N];
+  // g: the slice's first piece (wave-uniform).  It passes through an empty
+  // asm so the compiler forms each step's addresses in place instead of
+  // keeping every unrolled step's 64-bit addresses live in registers.
+  __device__ __forceinline__ void load(const u32x4* g, int tid) {
+    asm volatile("" : "+s"(g));
+#pragma unroll
+    for (int i = 0; i < N; ++i) r[i] = g[tid + i * kWideThreads];
+  }
+  __device__ __forceinline__ void store(u32x4* l, int tid) const {
+#pragma unroll
+    for (int i = 0; i < N; ++i) l[tid + i * kWideThreads] = r[i];
+  }
+};
+
+// The B operand of one K-step (every split term) as 32-bit words, built one
+// pair of operand slots at a time: bfloat16 terms take a word per pair, FP8
+// half a word.
+template <int P>
+struct OpWords {
+  static constexpr int NS = PrecTraits<P>::splits;
+  static constexpr int NW = PrecTraits<P>::fp8 ? 2 : 4;
+  uint32_t w[NS][NW];
+  __device__ __forceinline__ BFragT<P> frag(int sp) const {
+    if constexpr (PrecTraits<P>::fp8) return (long)(((unsigned long)w[0][1] << 32) | (unsigned long)w[0][0]);
+    else return __builtin_bit_cast(bf16x8, make_uint4(w[sp][0], w[sp][1], w[sp][2], w[sp][3]));
+  }
+  // slots 2 p and 2 p + 1 from their activation values
+  __device__ __forceinline__ void put_pair(int p, float v0, float v1, float inv) {
+    if constexpr (PrecTraits<P>::fp8) {
+      const float q0 = fminf(v0 * inv, 448.0f), q1 = fminf(v1 * inv, 448.0f);
+      if (p & 1) w[0][p >> 1] = __builtin_amdgcn_cvt_pk_fp8_f32(q0, q1, w[0][p >> 1], true);
+      else w[0][p >> 1] = __builtin_amdgcn_cvt_pk_fp8_f32(q0, q1, 0u, false);
+    } else {
+#pragma unroll
+      for (int sp = 0; sp < NS; ++sp) {
+        const uint32_t x = pack_bf16(v0, v1);
+        w[sp][p] = x;
+        if (sp + 1 < NS) {
+          v0 -= bf16_lo(x);
+          v1 -= bf16_hi(x);
+        }
+      }
+    }
+  }
+};
+
+// Operand slots 2 p, 2 p + 1 of K-step ks of the first hidden layer: layer 1
+// (softplus of the point's product with W1[:, 0..2] plus the folded latent
+// term of the row's gate) at the slots' neurons.
+template <int P, int H>
+__device__ __forceinline__ void wide_l1_pair(const Views& V, const float (&pt)[4], int ks, int hq, int p, float inv,
+                                             OpWords<P>& o) {
+  const int n0 = wide_input(ks, hq, 2 * p);
+  const float2 c = *(const float2*)(V.cf + (int)pt[3] * H + n0);
+  const float4 w0 = *(const float4*)(V.w1p + 4 * n0);
+  const float4 w1 = *(const float4*)(V.w1p + 4 * (n0 + 1));
+  const float v0 = softplus_fast(fmaf(w0.x, pt[0], fmaf(w0.y, pt[1], fmaf(w0.z, pt[2], c.x))));
+  const float v1 = softplus_fast(fmaf(w1.x, pt[0], fmaf(w1.y, pt[1], fmaf(w1.z, pt[2], c.y))));
+  o.put_pair(p, v0, v1, inv);
+}
+
+// Operand slots 2 p, 2 p + 1 of K-step ks of the next hidden layer from the
+// previous layer's accumulators (FP8: scaled, plus the bias; the bfloat16
+// kinds start the accumulators at the bias).
+template <int P, int H>
+__device__ __forceinline__ void wide_epi_pair(const f32x4 (&acc)[H / 16], const float* hb, float scale, int ks, int hq,
+                                              int p, float inv, OpWords<P>& o) {
+  f32x4 a = acc[2 * ks + (p >> 1)];
+  // the accumulators stay in the accumulation registers until their use
+  asm volatile("" : "+a"(a));
+  const int e = 2 * (p & 1);
+  float v0 = a[e], v1 = a[e + 1];
+  if constexpr (PrecTraits<P>::fp8) {
+    const float2 bb = *(const float2*)(hb + wide_input(ks, hq, 2 * p));
+    v0 = fmaf(v0, scale, bb.x);
+    v1 = fmaf(v1, scale, bb.y);
+  }
+  o.put_pair(p, softplus_fast(v0), softplus_fast(v1), inv);
+}
+
+// One K-step: acc[nb] += W(slice)[nb] x operand for the H / 16 neuron blocks,
+// in regions of 4 blocks that each read the next region's weight fragments
+// from LDS ahead and run one pair of the next K-step's operand slots
+// (prep(p), p < 4) beside their products.
+template <int P, int H, class Prep>
+__device__ __forceinline__ void wide_step(const char* slice, int lane, const OpWords<P>& b, f32x4 (&acc)[H / 16],
+                                          Prep&& prep) {
+  constexpr int NS = PrecTraits<P>::splits;
+  constexpr int GR = 4, NG = H / 16 / GR;
+  BFragT<P> bf[NS];
+#pragma unroll
+  for (int sp = 0; sp < NS; ++sp) bf[sp] = b.frag(sp);
+  FragT<P> a[2][GR];
+#pragma unroll
+  for (int i = 0; i < GR; ++i) a[0][i] = *(const FragT<P>*)(slice + (size_t)(i * 64 + lane) * frag_bytes<P>());
+#pragma unroll
+  for (int g = 0; g < NG; ++g) {
+    if (g + 1 < NG)
+#pragma unroll
+      for (int i = 0; i < GR; ++i)
+        a[(g + 1) & 1][i] = *(const FragT<P>*)(slice + (size_t)(((g + 1) * GR + i) * 64 + lane) * frag_bytes<P>());
+#pragma unroll
+    for (int i = 0; i < GR; ++i)
+#pragma unroll
+      for (int sp = 0; sp < NS; ++sp) {
+        f32x4& c = acc[g * GR + i];
+        if constexpr (PrecTraits<P>::fp8) c = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a[g & 1][i], bf[sp], c, 0, 0, 0);
+        else c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[g & 1][i], bf[sp], c, 0, 0, 0);
+      }
+    if (g < 4) prep(g);
+    sched_fence();
+  }
+}
+
+template <int P, int H>
+__device__ __forceinline__ void wide_acc_init(const float* hb, int hq, f32x4 (&acc)[H / 16]) {
+#pragma unroll
+  for (int nb = 0; nb < H / 16; ++nb) {
+    if constexpr (PrecTraits<P>::fp8) acc[nb] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    else acc[nb] = *(const f32x4*)(hb + 16 * nb + 4 * hq);
+  }
+}
+
+// Output of the last hidden layer for the wave's block c: softplus, dot with
+// the output weights, sum over the row's 4 lane groups, max over each
+// position's gates, hinge into the tile's table.
+template <int P, int H>
+__device__ __forceinline__ void wide_output(const Views& V, const EdgeConsts& e, const f32x4 (&acc)[H / 16],
+                                            const float* hb, float scale, int c, int hq, int lane) {
+  float op = 0.0f;
+#pragma unroll
+  for (int nb = 0; nb < H / 16; ++nb) {
+    const float4 o4 = *(const float4*)(V.wo + 16 * nb + 4 * hq);
+    float4 bb = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if constexpr (PrecTraits<P>::fp8) bb = *(const float4*)(hb + 16 * nb + 4 * hq);
+    const float ow[4] = {o4.x, o4.y, o4.z, o4.w}, bv[4] = {bb.x, bb.y, bb.z, bb.w};
+    f32x4 a = acc[nb];
+    asm volatile("" : "+a"(a));
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      op = fmaf(ow[i], softplus_fast(PrecTraits<P>::fp8 ? fmaf(a[i], scale, bv[i]) : a[i]), op);
+  }
+  op += __shfl_xor(op, 16, 64);
+  op += __shfl_xor(op, 32, 64);
+  const float sv = op + e.bout;
+  const int base = e.p * e.G;
+  float best = sv;
+  for (int g = 1; g < e.G; ++g) {
+    const float o = __shfl(sv, base + g, 64);
+    if (base + g < kRows) best = fmaxf(best, o);
+  }
+  const int q = c * e.Pc + e.p;
+  if (lane < kRows && e.g == 0 && e.p < e.Pc && q < e.npos) V.hinge[q] = fmaxf(0.0f, e.dsafe - best);
+}
+
+template <int P, int H, int NHH>
+__global__ __launch_bounds__(kWideThreads, 1) void k_wide(FusedBatch batch, DeviceWeights w, int Tm, int Gm,
+                                                           int max_tiles) {
+  using PT = PrecTraits<P>;
+  constexpr int NS = PT::splits;
+  constexpr int KS = H / 32;
+  constexpr int SB = wide_slice_bytes<P, H>();
+  constexpr int SPP = NHH * KS;                 // steps (slices) per pass
+  extern __shared__ __align__(16) char lds[];
+  const Views V = make_wide_views<P, H, NHH>(lds, Tm, Gm, max_tiles);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int hq = lane >> 4, nl = lane & 15;
+  const u32x4* gw = (const u32x4*)w.hidden_lp;
+  u32x4* ring = (u32x4*)V.act;
+  for (int i = tid; i < 4 * H; i += kWideThreads) V.w1p[i] = w.w1p[i];
+  for (int i = tid; i < NHH * H; i += kWideThreads) V.hb[i] = w.hbias[i];
+  for (int i = tid; i < H; i += kWideThreads) V.wo[i] = w.wout[i];
+  const float inv1 = PT::fp8 ? w.a_inv[0] : 1.0f;
+  const float invB = (PT::fp8 && NHH == 2) ? w.a_inv[NHH - 1] : 1.0f;
+  const float sA = PT::fp8 ? w.w_scale[0] * w.a_scale[0] : 1.0f;
+  const float sB = PT::fp8 ? w.w_scale[NHH - 1] * w.a_scale[NHH - 1] : 1.0f;
+
+  while (true) {
+    __syncthreads();
+    if (tid == 0) V.misc[0] = (int)atomicAdd(batch.tile_counter, 1u);
+    __syncthreads();
+    const int tile = V.misc[0];
+    if (tile >= batch.n_tiles) break;
+    const int2 tl = batch.tiles[tile];
+    const SolveDesc& d = batch.descs[tl.x];
+    const int k0 = tl.y;
+    const int Re = min(kTileR, d.K - k0);
+    const uint32_t tick = d.tick_fixed == 0xFFFFFFFFu ? *d.tick_slot : d.tick_fixed;
+    tile_prologue(V, d, k0, Re, tick, H);
+    const int npos = Re * d.T;
+    const int nblk = (npos + kRows / d.G - 1) / (kRows / d.G);
+    const int npass = (nblk + kWideWaves - 1) / kWideWaves;
+    const EdgeConsts ec = edge_consts(d, nl, npos, w.bout);
+    for (int i = tid; i < SB / 16; i += kWideThreads) ring[i] = gw[i];
+    __syncthreads();
+    for (int j = 0; j < npass; ++j) {
+      const int c = j * kWideWaves + wave;
+      alignas(16) float pt[4];
+      chunk_point(V, ec, c, pt);
+      // ---- first hidden layer: K-steps 0 .. KS-1 use ring slots ks & 1
+      f32x4 accA[H / 16];
+      wide_acc_init<P, H>(V.hb, hq, accA);
+      OpWords<P> bc;
+#pragma unroll
+      for (int p = 0; p < 4; ++p) wide_l1_pair<P, H>(V, pt, 0, hq, p, inv1, bc);
+      for (int ks = 0; ks < KS; ++ks) {
+        // the next step's slice (after the tile's last step: slice 0 again,
+        // unused; an unconditional copy keeps the staging in registers)
+        const int nxt = ks + 1 < SPP ? ks + 1 : 0;
+        SliceCopy<P, H> pf;
+        pf.load(gw + (size_t)nxt * (SB / 16), tid);
+        OpWords<P> bn;
+        const int kn = ks + 1 < KS ? ks + 1 : ks;    // the last step's prep is unused
+        wide_step<P, H>(V.act + (ks & 1) * SB, lane, bc, accA,
+                        [&](int p) { wide_l1_pair<P, H>(V, pt, kn, hq, p, inv1, bn); });
+        pf.store(ring + ((ks + 1) & 1) * (SB / 16), tid);
+        __syncthreads();
+        bc = bn;
+      }
+      if constexpr (NHH == 2) {
+        // ---- second hidden layer: operands from accA, K-step by K-step
+        f32x4 accB[H / 16];
+        wide_acc_init<P, H>(V.hb + H, hq, accB);
+#pragma unroll
+        for (int p = 0; p < 4; ++p) wide_epi_pair<P, H>(accA, V.hb, sA, 0, hq, p, invB, bc);
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+          const int nxt = KS + ks + 1 < SPP ? KS + ks + 1 : 0;
+          SliceCopy<P, H> pf;
+          pf.load(gw + (size_t)nxt * (SB / 16), tid);
+          OpWords<P> bn;
+          wide_step<P, H>(V.act + (ks & 1) * SB, lane, bc, accB, [&](int p) {
+            if (ks + 1 < KS) wide_epi_pair<P, H>(accA, V.hb, sA, ks + 1, hq, p, invB, bn);
+          });
+          pf.store(ring + ((ks + 1) & 1) * (SB / 16), tid);
+          __syncthreads();
+          bc = bn;
+        }
+        wide_output<P, H>(V, ec, accB, V.hb + H, sB, c, hq, lane);
+      } else {
+        wide_output<P, H>(V, ec, accA, V.hb, sA, c, hq, lane);
+      }
+    }
+    __syncthreads();
+    tile_epilogue(V, d, k0, Re, tick);
+  }
+}
+
 // ------------------------------------------------------------------ host side
 
 template <int P, int H, int NHH>
@@ -826,6 +1162,31 @@ static hipError_t launch_fused_t(const FusedBatch& b, const DeviceWeights& w, in
   return hipGetLastError();
 }
 
+template <int P, int H, int NHH>
+static hipError_t launch_wide_t(const FusedBatch& b, const DeviceWeights& w, int Tm, int Gm,
+                                int max_tiles, hipStream_t s) {
+  const FusedLds L = wide_lds<P, H, NHH>(Tm, Gm, max_tiles);
+  {
+    static std::mutex mu;
+    static int max_set = 0;
+    std::lock_guard<std::mutex> lock(mu);
+    if ((int)L.total > max_set) {
+      hipError_t e = hipFuncSetAttribute((const void*)k_wide<P, H, NHH>,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.total);
+      if (e != hipSuccess) return e;
+      max_set = (int)L.total;
+    }
+  }
+  int dev = 0, ncu = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  const int grid = std::max(1, std::min(b.n_tiles, ncu));
+  hipLaunchKernelGGL((k_wide<P, H, NHH>), dim3(grid), dim3(kWideThreads), L.total, s, b, w, Tm, Gm,
+                     max_tiles);
+  return hipGetLastError();
+}
+
 template <int P>
 static hipError_t launch_fused_p(const FusedBatch& b, const DeviceWeights& w, int Tm, int Gm, int mt,
                                  hipStream_t s) {
@@ -834,6 +1195,8 @@ static hipError_t launch_fused_p(const FusedBatch& b, const DeviceWeights& w, in
   if (w.H == 128 && nhh == 2) return launch_fused_t<P, 128, 2>(b, w, Tm, Gm, mt, s);
   if (w.H == 256 && nhh == 1) return launch_fused_t<P, 256, 1>(b, w, Tm, Gm, mt, s);
   if (w.H == 256 && nhh == 2) return launch_fused_t<P, 256, 2>(b, w, Tm, Gm, mt, s);
+  if (w.H == 512 && nhh == 1) return launch_wide_t<P, 512, 1>(b, w, Tm, Gm, mt, s);
+  if (w.H == 512 && nhh == 2) return launch_wide_t<P, 512, 2>(b, w, Tm, Gm, mt, s);
   return hipErrorInvalidValue;
 }
 
@@ -861,12 +1224,14 @@ int fused_tile_rollouts(int, int, int) { return kTileR; }
 
 bool fused_supported(int precision, int H, int n_hidden) {
   if (!(precision == P_BF16 || precision == P_BF16X2 || precision == P_BF16X3 || precision == P_FP8)) return false;
-  return (H == 128 || H == 256) && (n_hidden == 2 || n_hidden == 3);
+  return (H == 128 || H == 256 || H == 512) && (n_hidden == 2 || n_hidden == 3);
 }
 
 size_t fused_lds_bytes(int precision, int H, int n_hidden, int Tm, int Gm, int max_tiles) {
   auto pick = [&](auto p_tag) -> size_t {
     constexpr int P = decltype(p_tag)::value;
+    if (H == 512)
+      return n_hidden == 2 ? wide_lds<P, 512, 1>(Tm, Gm, max_tiles).total : wide_lds<P, 512, 2>(Tm, Gm, max_tiles).total;
     if (n_hidden == 2)
       return H == 128 ? fused_lds<P, 128, 1>(Tm, Gm, max_tiles).total : fused_lds<P, 256, 1>(Tm, Gm, max_tiles).total;
     return H == 128 ? fused_lds<P, 128, 2>(Tm, Gm, max_tiles).total : fused_lds<P, 256, 2>(Tm, Gm, max_tiles).total;
@@ -935,15 +1300,19 @@ int pack_lowp_weights(int precision, int H, int n_hidden, const mppi_sdf_weights
       a_scale[l] = as;
       a_inv[l] = 1.0f / as;
     }
-    // fragment (l, nb, ks, lane) at (((l NB + nb) KS + ks) 64 + lane), as
-    // frag_index<H> lays it out
+    // H <= 256: fragment (l, nb, ks, lane) at (((l NB + nb) KS + ks) 64 + lane),
+    // as frag_index<H> lays it out, operand slot j = input 32 ks + 8 (lane / 16) + j.
+    // H = 512: slices (l KS + ks) of NB fragments, ((l KS + ks) NB + nb) 64 + lane,
+    // operand slot j = input wide_input(ks, lane / 16, j).
+    const bool wide = H == 512;
     for (int nb = 0; nb < NB; ++nb)
       for (int ks = 0; ks < KS; ++ks)
         for (int lane = 0; lane < 64; ++lane) {
           const int m = 16 * nb + lane % 16;
-          const size_t fi = (((size_t)l * NB + nb) * KS + ks) * 64 + lane;
+          const size_t fi = wide ? (((size_t)l * KS + ks) * NB + nb) * 64 + lane
+                                 : (((size_t)l * NB + nb) * KS + ks) * 64 + lane;
           for (int j = 0; j < 8; ++j) {
-            const int k = 32 * ks + 8 * (lane / 16) + j;
+            const int k = wide ? wide_input(ks, lane / 16, j) : 32 * ks + 8 * (lane / 16) + j;
             const float v = W[(size_t)m * H + k];
             if (fp8) {
               blob[fi * 8 + j] = host_e4m3(v / scale);
