@@ -101,7 +101,7 @@ __host__ __device__ constexpr size_t act_buf_bytes() {
 }
 
 struct FusedLds {
-  size_t act, w1p, hb, wo, cf, rt, base, los, dp, hinge, pts, opart, jl, wt, fac, misc, total;
+  size_t act, w1p, hb, wo, cf, rt, base, los, dp, hinge, pts, opart, jl, wt, fac, misc, xch, total;
 };
 
 // The activation buffers (input of hidden layer l, block parity p) share
@@ -148,7 +148,7 @@ __host__ __device__ constexpr size_t frag_index(int l, int nb, int ks, int lane)
 
 // Shared-memory views of one workgroup.
 struct Views {
-  char* act;
+  char *act, *xch;
   float *samp, *w1p, *hb, *wo, *cf, *rt, *base, *los, *dp, *hinge, *pts, *opart, *jl;
   double *wt, *fac;
   int* misc;
@@ -157,7 +157,7 @@ struct Views {
 template <int P, int H, int NHH>
 __device__ __forceinline__ Views make_views(char* lds, int Tm, int Gm, int max_tiles) {
   const FusedLds L = fused_lds<P, H, NHH>(Tm, Gm, max_tiles);
-  Views v;
+  Views v{};
   v.act = lds + L.act;
   v.samp = (float*)(lds + L.act);
   v.w1p = (float*)(lds + L.w1p);
@@ -802,22 +802,25 @@ __global__ __launch_bounds__(kMergeThreads) void k_fused_merge(FusedBatch batch)
 // At H = 512 a hidden layer's bfloat16 weights (512 KB) no longer fit in a
 // compute unit, so the decoder streams them: the weights of one K-step of
 // 32 inputs for all H neurons (one "slice", 32 KB in bfloat16, 16 KB in FP8)
-// pass from L2 through a two-slice LDS ring that the workgroup's 4 waves
-// share, one slice per step with one barrier per step, while each wave keeps
-// its own 16 query rows in registers through every layer.  A layer's FP32
-// accumulators of 16 rows x H neurons (128 VGPRs per lane) turn into the next
-// layer's matrix-core operands without leaving the registers: a lane holds
-// neurons 16 nb + 4 (lane / 16) + i of its row in accumulator block nb, and the
+// pass from L2 through a two-slice LDS ring, one slice per step with one
+// workgroup barrier per step, while the query rows stay in registers through
+// every layer.  Eight waves, two per SIMD: a pair of waves shares a block of
+// 16 rows, each owning the neuron blocks of one parity (nb = 2 m + par), so a
+// wave keeps 16 x 256 FP32 accumulators per layer (64 registers).  The
 // weights are packed with their input index permuted so that the 8 operand
-// values of K-step ks are exactly the lane's values of accumulator blocks
-// 2 ks and 2 ks + 1 (the product is the same sum in another order).  Layer 1
-// is evaluated K-step by K-step from the row's gate-frame point in the same
-// order.  One wave per SIMD (up to 512 registers): the matrix cores and the
-// vector units overlap inside the wave, the next K-step's operands being
-// formed while the current K-step's products run.
+// slots of K-step ks are the values of neuron blocks 2 ks (slots 0-3) and
+// 2 ks + 1 (slots 4-7) as one lane holds them in its accumulators (the
+// product is the same sum in another order): each wave of a pair forms its
+// half of the next K-step's operand from its own accumulators (or, for the
+// first hidden layer, from layer 1 at the row's gate-frame point) and the
+// two halves meet in a small LDS exchange buffer.  The two waves on a SIMD
+// run each step in opposite order (vector work first / products first) so
+// that one's vector work issues beside the other's matrix-core products.
 
-constexpr int kWideWaves = 4;
+constexpr int kWideWaves = 8;
 constexpr int kWideThreads = 64 * kWideWaves;
+constexpr int kWidePairs = kWideWaves / 2;      // row blocks of 16 per pass
+constexpr int kWideRegion = 4;                  // owned neuron blocks per scheduling region
 
 template <int P> __host__ __device__ constexpr int frag_bytes() { return PrecTraits<P>::fp8 ? 8 : 16; }
 
@@ -830,12 +833,21 @@ __host__ __device__ constexpr int wide_input(int ks, int hq, int j) {
   return 32 * ks + (j < 4 ? 4 * hq + j : 16 + 4 * hq + (j - 4));
 }
 
+// Operand exchange buffer: per pair, per step parity, per split term, per
+// lane one operand (16 bytes bfloat16, 8 bytes FP8).
+template <int P> __host__ __device__ constexpr int wide_xterm_bytes() { return 64 * frag_bytes<P>(); }
+template <int P> __host__ __device__ constexpr int wide_xbuf_bytes() {
+  return kWidePairs * 2 * PrecTraits<P>::splits * wide_xterm_bytes<P>();
+}
+
 template <int P, int H, int NHH>
 __host__ __device__ FusedLds wide_lds(int Tm, int Gm, int max_tiles) {
   FusedLds L{};
   size_t o = 0;
   auto take = [&](size_t b) { const size_t r = o; o = (o + b + 15) / 16 * 16; return r; };
   L.act = take(2 * (size_t)wide_slice_bytes<P, H>());     // weight slice ring
+  L.xch = take(wide_xbuf_bytes<P>());
+  L.opart = take(sizeof(float) * kWidePairs * 2 * kRows);
   L.w1p = take(sizeof(float) * 4 * H);
   L.hb = take(sizeof(float) * NHH * H);
   L.wo = take(sizeof(float) * H);
@@ -859,7 +871,9 @@ __device__ __forceinline__ Views make_wide_views(char* lds, int Tm, int Gm, int 
   const FusedLds L = wide_lds<P, H, NHH>(Tm, Gm, max_tiles);
   Views v{};
   v.act = lds + L.act;
+  v.xch = lds + L.xch;
   v.samp = (float*)(lds + L.pts);
+  v.opart = (float*)(lds + L.opart);
   v.w1p = (float*)(lds + L.w1p);
   v.hb = (float*)(lds + L.hb);
   v.wo = (float*)(lds + L.wo);
@@ -899,137 +913,153 @@ struct SliceCopy {
   }
 };
 
-// The B operand of one K-step (every split term) as 32-bit words, built one
-// pair of operand slots at a time: bfloat16 terms take a word per pair, FP8
-// half a word.
+// This wave's half (slots 4 par .. 4 par + 3) of one K-step's operand from
+// its 4 activation values, into the exchange buffer x (the pair's buffer of
+// the step's parity): bfloat16 splits a = hi (+ mid (+ lo)), two words per
+// term; FP8 one word.
 template <int P>
-struct OpWords {
-  static constexpr int NS = PrecTraits<P>::splits;
-  static constexpr int NW = PrecTraits<P>::fp8 ? 2 : 4;
-  uint32_t w[NS][NW];
-  __device__ __forceinline__ BFragT<P> frag(int sp) const {
-    if constexpr (PrecTraits<P>::fp8) return (long)(((unsigned long)w[0][1] << 32) | (unsigned long)w[0][0]);
-    else return __builtin_bit_cast(bf16x8, make_uint4(w[sp][0], w[sp][1], w[sp][2], w[sp][3]));
-  }
-  // slots 2 p and 2 p + 1 from their activation values
-  __device__ __forceinline__ void put_pair(int p, float v0, float v1, float inv) {
-    if constexpr (PrecTraits<P>::fp8) {
-      const float q0 = fminf(v0 * inv, 448.0f), q1 = fminf(v1 * inv, 448.0f);
-      if (p & 1) w[0][p >> 1] = __builtin_amdgcn_cvt_pk_fp8_f32(q0, q1, w[0][p >> 1], true);
-      else w[0][p >> 1] = __builtin_amdgcn_cvt_pk_fp8_f32(q0, q1, 0u, false);
-    } else {
+__device__ __forceinline__ void wide_put_half(char* x, int lane, int par, float (&v)[4], float inv) {
+  using PT = PrecTraits<P>;
+  if constexpr (PT::fp8) {
+    float q[4];
 #pragma unroll
-      for (int sp = 0; sp < NS; ++sp) {
-        const uint32_t x = pack_bf16(v0, v1);
-        w[sp][p] = x;
-        if (sp + 1 < NS) {
-          v0 -= bf16_lo(x);
-          v1 -= bf16_hi(x);
-        }
+    for (int i = 0; i < 4; ++i) q[i] = fminf(v[i] * inv, 448.0f);
+    uint32_t w = __builtin_amdgcn_cvt_pk_fp8_f32(q[0], q[1], 0u, false);
+    w = __builtin_amdgcn_cvt_pk_fp8_f32(q[2], q[3], w, true);
+    *(uint32_t*)(x + lane * 8 + 4 * par) = w;
+  } else {
+#pragma unroll
+    for (int sp = 0; sp < PT::splits; ++sp) {
+      const uint32_t w0 = pack_bf16(v[0], v[1]), w1 = pack_bf16(v[2], v[3]);
+      *(uint2*)(x + sp * wide_xterm_bytes<P>() + lane * 16 + 8 * par) = make_uint2(w0, w1);
+      if (sp + 1 < PT::splits) {
+        v[0] -= bf16_lo(w0);
+        v[1] -= bf16_hi(w0);
+        v[2] -= bf16_lo(w1);
+        v[3] -= bf16_hi(w1);
       }
     }
   }
-};
-
-// Operand slots 2 p, 2 p + 1 of K-step ks of the first hidden layer: layer 1
-// (softplus of the point's product with W1[:, 0..2] plus the folded latent
-// term of the row's gate) at the slots' neurons.
-template <int P, int H>
-__device__ __forceinline__ void wide_l1_pair(const Views& V, const float (&pt)[4], int ks, int hq, int p, float inv,
-                                             OpWords<P>& o) {
-  const int n0 = wide_input(ks, hq, 2 * p);
-  const float2 c = *(const float2*)(V.cf + (int)pt[3] * H + n0);
-  const float4 w0 = *(const float4*)(V.w1p + 4 * n0);
-  const float4 w1 = *(const float4*)(V.w1p + 4 * (n0 + 1));
-  const float v0 = softplus_fast(fmaf(w0.x, pt[0], fmaf(w0.y, pt[1], fmaf(w0.z, pt[2], c.x))));
-  const float v1 = softplus_fast(fmaf(w1.x, pt[0], fmaf(w1.y, pt[1], fmaf(w1.z, pt[2], c.y))));
-  o.put_pair(p, v0, v1, inv);
 }
 
-// Operand slots 2 p, 2 p + 1 of K-step ks of the next hidden layer from the
-// previous layer's accumulators (FP8: scaled, plus the bias; the bfloat16
-// kinds start the accumulators at the bias).
+// Half operand of K-step ks of the first hidden layer: layer 1 (softplus of
+// the point's product with W1[:, 0..2] plus the folded latent term of the
+// row's gate) at neurons 32 ks + 16 par + 4 hq + i.
 template <int P, int H>
-__device__ __forceinline__ void wide_epi_pair(const f32x4 (&acc)[H / 16], const float* hb, float scale, int ks, int hq,
-                                              int p, float inv, OpWords<P>& o) {
-  f32x4 a = acc[2 * ks + (p >> 1)];
-  // the accumulators stay in the accumulation registers until their use
-  asm volatile("" : "+a"(a));
-  const int e = 2 * (p & 1);
-  float v0 = a[e], v1 = a[e + 1];
-  if constexpr (PrecTraits<P>::fp8) {
-    const float2 bb = *(const float2*)(hb + wide_input(ks, hq, 2 * p));
-    v0 = fmaf(v0, scale, bb.x);
-    v1 = fmaf(v1, scale, bb.y);
+__device__ __forceinline__ void wide_l1_half(const Views& V, const float (&pt)[4], int ks, int hq, int par, int lane,
+                                             float inv, char* x) {
+  const int n0 = 32 * ks + 16 * par + 4 * hq;
+  const float4 c = *(const float4*)(V.cf + (int)pt[3] * H + n0);
+  const float cc[4] = {c.x, c.y, c.z, c.w};
+  float v[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const float4 w = *(const float4*)(V.w1p + 4 * (n0 + i));
+    v[i] = softplus_fast(fmaf(w.x, pt[0], fmaf(w.y, pt[1], fmaf(w.z, pt[2], cc[i]))));
   }
-  o.put_pair(p, softplus_fast(v0), softplus_fast(v1), inv);
+  wide_put_half<P>(x, lane, par, v, inv);
 }
 
-// One K-step: acc[nb] += W(slice)[nb] x operand for the H / 16 neuron blocks,
-// in regions of 4 blocks that each read the next region's weight fragments
-// from LDS ahead and run one pair of the next K-step's operand slots
-// (prep(p), p < 4) beside their products.
-template <int P, int H, class Prep>
-__device__ __forceinline__ void wide_step(const char* slice, int lane, const OpWords<P>& b, f32x4 (&acc)[H / 16],
-                                          Prep&& prep) {
-  constexpr int NS = PrecTraits<P>::splits;
-  constexpr int GR = 4, NG = H / 16 / GR;
+// Half operand of K-step ks of the next hidden layer from this wave's
+// accumulator block m = ks (neurons 32 ks + 16 par + 4 hq + i); FP8: scaled,
+// plus the bias (the bfloat16 kinds start the accumulators at the bias).
+template <int P>
+__device__ __forceinline__ void wide_epi_half(const f32x4& acc, const float* hb, float scale, int ks, int hq, int par,
+                                              int lane, float inv, char* x) {
+  float v[4];
+  float4 bb = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  if constexpr (PrecTraits<P>::fp8) bb = *(const float4*)(hb + 32 * ks + 16 * par + 4 * hq);
+  const float bv[4] = {bb.x, bb.y, bb.z, bb.w};
+#pragma unroll
+  for (int i = 0; i < 4; ++i) v[i] = softplus_fast(PrecTraits<P>::fp8 ? fmaf(acc[i], scale, bv[i]) : acc[i]);
+  wide_put_half<P>(x, lane, par, v, inv);
+}
+
+// One K-step of one wave: acc[m] += W(slice)[2 m + par] x operand for its
+// H / 32 neuron blocks, in regions of kWideRegion blocks that read the next
+// region's weight fragments ahead; the first region also issues the global
+// reads of the next slice, the last one its LDS stores.  prep() forms this
+// wave's half of the next K-step's operand: before the products when VFIRST,
+// after them otherwise.
+template <int P, int H, bool VFIRST, class Prep>
+__device__ __forceinline__ void wide_step(const char* slice, const char* xin, int lane, int par, f32x4 (&acc)[H / 32],
+                                          Prep&& prep, SliceCopy<P, H>& pf, const u32x4* gsrc, u32x4* ldst, int tid) {
+  using PT = PrecTraits<P>;
+  constexpr int NS = PT::splits;
+  constexpr int GR = kWideRegion, NG = H / 32 / GR;
   BFragT<P> bf[NS];
 #pragma unroll
-  for (int sp = 0; sp < NS; ++sp) bf[sp] = b.frag(sp);
-  FragT<P> a[2][GR];
-#pragma unroll
-  for (int i = 0; i < GR; ++i) a[0][i] = *(const FragT<P>*)(slice + (size_t)(i * 64 + lane) * frag_bytes<P>());
-#pragma unroll
-  for (int g = 0; g < NG; ++g) {
-    if (g + 1 < NG)
-#pragma unroll
-      for (int i = 0; i < GR; ++i)
-        a[(g + 1) & 1][i] = *(const FragT<P>*)(slice + (size_t)(((g + 1) * GR + i) * 64 + lane) * frag_bytes<P>());
-#pragma unroll
-    for (int i = 0; i < GR; ++i)
-#pragma unroll
-      for (int sp = 0; sp < NS; ++sp) {
-        f32x4& c = acc[g * GR + i];
-        if constexpr (PrecTraits<P>::fp8) c = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a[g & 1][i], bf[sp], c, 0, 0, 0);
-        else c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[g & 1][i], bf[sp], c, 0, 0, 0);
-      }
-    if (g < 4) prep(g);
+  for (int sp = 0; sp < NS; ++sp) {
+    if constexpr (PT::fp8) bf[sp] = *(const long*)(xin + lane * 8);
+    else bf[sp] = __builtin_bit_cast(bf16x8, *(const uint4*)(xin + sp * wide_xterm_bytes<P>() + lane * 16));
+  }
+  if constexpr (VFIRST) {
+    prep();
     sched_fence();
   }
+  pf.load(gsrc, tid);
+  const char* fb = slice + (size_t)(par * 64 + lane) * frag_bytes<P>();   // fragment 2 m + par at m * 128 lanes
+  FragT<P> a[2][GR];
+  auto fetch = [&](int g) {
+#pragma unroll
+    for (int i = 0; i < GR; ++i) a[g & 1][i] = *(const FragT<P>*)(fb + (size_t)(g * GR + i) * 128 * frag_bytes<P>());
+  };
+  fetch(0);
+#pragma unroll
+  for (int g = 0; g < NG; ++g) {
+    if (g + 1 < NG) fetch(g + 1);
+    if (g == NG - 1) pf.store(ldst, tid);
+#pragma unroll
+    for (int sp = 0; sp < NS; ++sp)
+#pragma unroll
+      for (int i = 0; i < GR; ++i) {
+        f32x4& c = acc[g * GR + i];
+        if constexpr (PT::fp8) c = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a[g & 1][i], bf[sp], c, 0, 0, 0);
+        else c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[g & 1][i], bf[sp], c, 0, 0, 0);
+      }
+    sched_fence();
+  }
+  if constexpr (!VFIRST) prep();
 }
 
 template <int P, int H>
-__device__ __forceinline__ void wide_acc_init(const float* hb, int hq, f32x4 (&acc)[H / 16]) {
+__device__ __forceinline__ void wide_acc_init(const float* hb, int hq, int par, f32x4 (&acc)[H / 32]) {
 #pragma unroll
-  for (int nb = 0; nb < H / 16; ++nb) {
-    if constexpr (PrecTraits<P>::fp8) acc[nb] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    else acc[nb] = *(const f32x4*)(hb + 16 * nb + 4 * hq);
+  for (int m = 0; m < H / 32; ++m) {
+    if constexpr (PrecTraits<P>::fp8) acc[m] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    else acc[m] = *(const f32x4*)(hb + 16 * (2 * m + par) + 4 * hq);
   }
 }
 
-// Output of the last hidden layer for the wave's block c: softplus, dot with
-// the output weights, sum over the row's 4 lane groups, max over each
-// position's gates, hinge into the tile's table.
+// This wave's share of the output of its row block: softplus of the last
+// hidden layer's owned neurons, dot with the output weights, summed over the
+// row's 4 lane groups, into the pair's partial table.
 template <int P, int H>
-__device__ __forceinline__ void wide_output(const Views& V, const EdgeConsts& e, const f32x4 (&acc)[H / 16],
-                                            const float* hb, float scale, int c, int hq, int lane) {
+__device__ __forceinline__ void wide_output_part(const Views& V, const f32x4 (&acc)[H / 32], const float* hb,
+                                                 float scale, int hq, int par, int lane, float* op_out) {
   float op = 0.0f;
 #pragma unroll
-  for (int nb = 0; nb < H / 16; ++nb) {
-    const float4 o4 = *(const float4*)(V.wo + 16 * nb + 4 * hq);
+  for (int m = 0; m < H / 32; ++m) {
+    const int n0 = 16 * (2 * m + par) + 4 * hq;
+    const float4 o4 = *(const float4*)(V.wo + n0);
     float4 bb = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    if constexpr (PrecTraits<P>::fp8) bb = *(const float4*)(hb + 16 * nb + 4 * hq);
+    if constexpr (PrecTraits<P>::fp8) bb = *(const float4*)(hb + n0);
     const float ow[4] = {o4.x, o4.y, o4.z, o4.w}, bv[4] = {bb.x, bb.y, bb.z, bb.w};
-    f32x4 a = acc[nb];
-    asm volatile("" : "+a"(a));
 #pragma unroll
     for (int i = 0; i < 4; ++i)
-      op = fmaf(ow[i], softplus_fast(PrecTraits<P>::fp8 ? fmaf(a[i], scale, bv[i]) : a[i]), op);
+      op = fmaf(ow[i], softplus_fast(PrecTraits<P>::fp8 ? fmaf(acc[m][i], scale, bv[i]) : acc[m][i]), op);
   }
   op += __shfl_xor(op, 16, 64);
   op += __shfl_xor(op, 32, 64);
-  const float sv = op + e.bout;
+  if (lane < kRows) op_out[par * kRows + lane] = op;
+}
+
+// Output of row block c from the pair's two partials: max over each
+// position's gates, hinge into the tile's table (lanes 0 .. 15).
+__device__ __forceinline__ void wide_output_rows(const Views& V, const EdgeConsts& e, const float* op_in, int c,
+                                                 int lane) {
+  const int row = lane & (kRows - 1);
+  const float sv = op_in[row] + op_in[kRows + row] + e.bout;
   const int base = e.p * e.G;
   float best = sv;
   for (int g = 1; g < e.G; ++g) {
@@ -1040,28 +1070,90 @@ __device__ __forceinline__ void wide_output(const Views& V, const EdgeConsts& e,
   if (lane < kRows && e.g == 0 && e.p < e.Pc && q < e.npos) V.hinge[q] = fmaxf(0.0f, e.dsafe - best);
 }
 
-template <int P, int H, int NHH>
-__global__ __launch_bounds__(kWideThreads, 1) void k_wide(FusedBatch batch, DeviceWeights w, int Tm, int Gm,
-                                                           int max_tiles) {
+template <int P, int H, int NHH, bool VFIRST>
+__device__ __forceinline__ void wide_tile(const Views& V, const DeviceWeights& w, const SolveDesc& d, int npos,
+                                          int wave, int lane, int tid) {
   using PT = PrecTraits<P>;
-  constexpr int NS = PT::splits;
   constexpr int KS = H / 32;
   constexpr int SB = wide_slice_bytes<P, H>();
   constexpr int SPP = NHH * KS;                 // steps (slices) per pass
-  extern __shared__ __align__(16) char lds[];
-  const Views V = make_wide_views<P, H, NHH>(lds, Tm, Gm, max_tiles);
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr int XB = PT::splits * wide_xterm_bytes<P>();
   const int hq = lane >> 4, nl = lane & 15;
+  const int rb = wave >> 1, par = wave & 1;
   const u32x4* gw = (const u32x4*)w.hidden_lp;
   u32x4* ring = (u32x4*)V.act;
-  for (int i = tid; i < 4 * H; i += kWideThreads) V.w1p[i] = w.w1p[i];
-  for (int i = tid; i < NHH * H; i += kWideThreads) V.hb[i] = w.hbias[i];
-  for (int i = tid; i < H; i += kWideThreads) V.wo[i] = w.wout[i];
+  char* xb = V.xch + rb * 2 * XB;                    // this pair's two exchange buffers
+  float* opp = V.opart + rb * 2 * kRows;
   const float inv1 = PT::fp8 ? w.a_inv[0] : 1.0f;
   const float invB = (PT::fp8 && NHH == 2) ? w.a_inv[NHH - 1] : 1.0f;
   const float sA = PT::fp8 ? w.w_scale[0] * w.a_scale[0] : 1.0f;
   const float sB = PT::fp8 ? w.w_scale[NHH - 1] * w.a_scale[NHH - 1] : 1.0f;
+  const int nblk = (npos + kRows / d.G - 1) / (kRows / d.G);
+  const int npass = (nblk + kWidePairs - 1) / kWidePairs;
+  const EdgeConsts ec = edge_consts(d, nl, npos, w.bout);
+  // slice 0 and the first operand of pass 0
+  for (int i = tid; i < SB / 16; i += kWideThreads) ring[i] = gw[i];
+  alignas(16) float pt[4];
+  chunk_point(V, ec, rb, pt);
+  wide_l1_half<P, H>(V, pt, 0, hq, par, lane, inv1, xb);
+  __syncthreads();
+  for (int j = 0; j < npass; ++j) {
+    const int c = j * kWidePairs + rb;
+    // ---- first hidden layer
+    f32x4 accA[H / 32];
+    wide_acc_init<P, H>(V.hb, hq, par, accA);
+    for (int ks = 0; ks < KS; ++ks) {
+      const int nxt = ks + 1 < SPP ? ks + 1 : 0;
+      SliceCopy<P, H> pf;
+      wide_step<P, H, VFIRST>(V.act + (ks & 1) * SB, xb + (ks & 1) * XB, lane, par, accA, [&]() {
+        if (ks + 1 < KS) {
+          wide_l1_half<P, H>(V, pt, ks + 1, hq, par, lane, inv1, xb + ((ks + 1) & 1) * XB);
+        } else if (NHH == 1) {
+          // the first operand of the next pass (unused after the last)
+          chunk_point(V, ec, c + kWidePairs, pt);
+          wide_l1_half<P, H>(V, pt, 0, hq, par, lane, inv1, xb);
+        }
+      }, pf, gw + (size_t)nxt * (SB / 16), ring + ((ks + 1) & 1) * (SB / 16), tid);
+      __syncthreads();
+    }
+    if constexpr (NHH == 2) {
+      // ---- second hidden layer, its first operand from the final accA
+      wide_epi_half<P>(accA[0], V.hb, sA, 0, hq, par, lane, invB, xb);
+      __syncthreads();
+      f32x4 accB[H / 32];
+      wide_acc_init<P, H>(V.hb + H, hq, par, accB);
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        const int nxt = KS + ks + 1 < SPP ? KS + ks + 1 : 0;
+        SliceCopy<P, H> pf;
+        wide_step<P, H, VFIRST>(V.act + (ks & 1) * SB, xb + (ks & 1) * XB, lane, par, accB, [&]() {
+          if (ks + 1 < KS) {
+            wide_epi_half<P>(accA[ks + 1], V.hb, sA, ks + 1, hq, par, lane, invB, xb + ((ks + 1) & 1) * XB);
+          } else {
+            chunk_point(V, ec, c + kWidePairs, pt);
+            wide_l1_half<P, H>(V, pt, 0, hq, par, lane, inv1, xb);
+          }
+        }, pf, gw + (size_t)nxt * (SB / 16), ring + ((ks + 1) & 1) * (SB / 16), tid);
+        __syncthreads();
+      }
+      wide_output_part<P, H>(V, accB, V.hb + H, sB, hq, par, lane, opp);
+    } else {
+      wide_output_part<P, H>(V, accA, V.hb, sA, hq, par, lane, opp);
+    }
+    __syncthreads();
+    if (par == 0) wide_output_rows(V, ec, opp, c, lane);
+  }
+}
 
+template <int P, int H, int NHH>
+__global__ __launch_bounds__(kWideThreads, 1) void k_wide(FusedBatch batch, DeviceWeights w, int Tm, int Gm,
+                                                           int max_tiles) {
+  extern __shared__ __align__(16) char lds[];
+  const Views V = make_wide_views<P, H, NHH>(lds, Tm, Gm, max_tiles);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int i = tid; i < 4 * H; i += kWideThreads) V.w1p[i] = w.w1p[i];
+  for (int i = tid; i < NHH * H; i += kWideThreads) V.hb[i] = w.hbias[i];
+  for (int i = tid; i < H; i += kWideThreads) V.wo[i] = w.wout[i];
   while (true) {
     __syncthreads();
     if (tid == 0) V.misc[0] = (int)atomicAdd(batch.tile_counter, 1u);
@@ -1074,60 +1166,10 @@ __global__ __launch_bounds__(kWideThreads, 1) void k_wide(FusedBatch batch, Devi
     const int Re = min(kTileR, d.K - k0);
     const uint32_t tick = d.tick_fixed == 0xFFFFFFFFu ? *d.tick_slot : d.tick_fixed;
     tile_prologue(V, d, k0, Re, tick, H);
-    const int npos = Re * d.T;
-    const int nblk = (npos + kRows / d.G - 1) / (kRows / d.G);
-    const int npass = (nblk + kWideWaves - 1) / kWideWaves;
-    const EdgeConsts ec = edge_consts(d, nl, npos, w.bout);
-    for (int i = tid; i < SB / 16; i += kWideThreads) ring[i] = gw[i];
-    __syncthreads();
-    for (int j = 0; j < npass; ++j) {
-      const int c = j * kWideWaves + wave;
-      alignas(16) float pt[4];
-      chunk_point(V, ec, c, pt);
-      // ---- first hidden layer: K-steps 0 .. KS-1 use ring slots ks & 1
-      f32x4 accA[H / 16];
-      wide_acc_init<P, H>(V.hb, hq, accA);
-      OpWords<P> bc;
-#pragma unroll
-      for (int p = 0; p < 4; ++p) wide_l1_pair<P, H>(V, pt, 0, hq, p, inv1, bc);
-      for (int ks = 0; ks < KS; ++ks) {
-        // the next step's slice (after the tile's last step: slice 0 again,
-        // unused; an unconditional copy keeps the staging in registers)
-        const int nxt = ks + 1 < SPP ? ks + 1 : 0;
-        SliceCopy<P, H> pf;
-        pf.load(gw + (size_t)nxt * (SB / 16), tid);
-        OpWords<P> bn;
-        const int kn = ks + 1 < KS ? ks + 1 : ks;    // the last step's prep is unused
-        wide_step<P, H>(V.act + (ks & 1) * SB, lane, bc, accA,
-                        [&](int p) { wide_l1_pair<P, H>(V, pt, kn, hq, p, inv1, bn); });
-        pf.store(ring + ((ks + 1) & 1) * (SB / 16), tid);
-        __syncthreads();
-        bc = bn;
-      }
-      if constexpr (NHH == 2) {
-        // ---- second hidden layer: operands from accA, K-step by K-step
-        f32x4 accB[H / 16];
-        wide_acc_init<P, H>(V.hb + H, hq, accB);
-#pragma unroll
-        for (int p = 0; p < 4; ++p) wide_epi_pair<P, H>(accA, V.hb, sA, 0, hq, p, invB, bc);
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-          const int nxt = KS + ks + 1 < SPP ? KS + ks + 1 : 0;
-          SliceCopy<P, H> pf;
-          pf.load(gw + (size_t)nxt * (SB / 16), tid);
-          OpWords<P> bn;
-          wide_step<P, H>(V.act + (ks & 1) * SB, lane, bc, accB, [&](int p) {
-            if (ks + 1 < KS) wide_epi_pair<P, H>(accA, V.hb, sA, ks + 1, hq, p, invB, bn);
-          });
-          pf.store(ring + ((ks + 1) & 1) * (SB / 16), tid);
-          __syncthreads();
-          bc = bn;
-        }
-        wide_output<P, H>(V, ec, accB, V.hb + H, sB, c, hq, lane);
-      } else {
-        wide_output<P, H>(V, ec, accA, V.hb, sA, c, hq, lane);
-      }
-    }
+    // waves w and w + 4 share a SIMD: one forms its operands before its
+    // products, the other after
+    if (wave < kWideWaves / 2) wide_tile<P, H, NHH, true>(V, w, d, Re * d.T, wave, lane, tid);
+    else wide_tile<P, H, NHH, false>(V, w, d, Re * d.T, wave, lane, tid);
     __syncthreads();
     tile_epilogue(V, d, k0, Re, tick);
   }
