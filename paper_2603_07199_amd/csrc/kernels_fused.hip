@@ -311,9 +311,11 @@ __device__ __forceinline__ void tile_noise(const Views& V, const SolveDesc& d, i
 }
 
 // Per-tile tables, noise and dynamics (all threads of the workgroup call it).
-__device__ void tile_prologue(const Views& V, const SolveDesc& d, int k0, int Re, uint32_t tick, int H) {
+// The folded latent rows go to V.cf with row stride H + cf_pad.
+__device__ void tile_prologue(const Views& V, const SolveDesc& d, int k0, int Re, uint32_t tick, int H,
+                              int cf_pad = 0) {
   const int tid = threadIdx.x, T = d.T, G = d.G;
-  for (int i = tid; i < G * H; i += (int)blockDim.x) V.cf[i] = d.cfold[i];
+  for (int i = tid; i < G * H; i += (int)blockDim.x) V.cf[i + (cf_pad ? (i / H) * cf_pad : 0)] = d.cfold[i];
   for (int i = tid; i < 9 * G; i += (int)blockDim.x) V.rt[i] = d.Rt[i];
   for (int i = tid; i < 3 * G * (T + 1); i += (int)blockDim.x) V.base[i] = d.base[i];
   if (d.Q_vis != 0.0f)
@@ -827,6 +829,10 @@ template <int P> __host__ __device__ constexpr int frag_bytes() { return PrecTra
 // Bytes of one weight slice: H / 16 fragments of 64 lanes.
 template <int P, int H> __host__ __device__ constexpr int wide_slice_bytes() { return (H / 16) * 64 * frag_bytes<P>(); }
 
+// Row stride of the folded latent table: the pad puts the gates' rows on
+// different LDS banks (rows of one block read up to 8 gates at once).
+template <int H> __host__ __device__ constexpr int wide_cf_stride() { return H + 4; }
+
 // Input neuron of operand slot j (< 8) of lane group hq (= lane / 16) in
 // K-step ks: the lane's accumulator values of blocks 2 ks and 2 ks + 1.
 __host__ __device__ constexpr int wide_input(int ks, int hq, int j) {
@@ -855,7 +861,7 @@ __host__ __device__ FusedLds wide_lds(int Tm, int Gm, int max_tiles) {
   L.wt = take(sizeof(double) * (kTileR + 4));
   L.misc = take(64);
   L.pts = take(sizeof(float) * 4 * kTileR * Tm);          // control samples
-  L.cf = take(sizeof(float) * Gm * H);
+  L.cf = take(sizeof(float) * Gm * wide_cf_stride<H>());
   L.rt = take(sizeof(float) * 9 * Gm);
   L.base = take(sizeof(float) * 3 * Gm * (Tm + 1));
   L.los = take(sizeof(float) * 2 * Tm);
@@ -949,7 +955,7 @@ template <int P, int H>
 __device__ __forceinline__ void wide_l1_half(const Views& V, const float (&pt)[4], int ks, int hq, int par, int lane,
                                              float inv, char* x) {
   const int n0 = 32 * ks + 16 * par + 4 * hq;
-  const float4 c = *(const float4*)(V.cf + (int)pt[3] * H + n0);
+  const float4 c = *(const float4*)(V.cf + (int)pt[3] * wide_cf_stride<H>() + n0);
   const float cc[4] = {c.x, c.y, c.z, c.w};
   float v[4];
 #pragma unroll
@@ -1165,7 +1171,7 @@ __global__ __launch_bounds__(kWideThreads, 1) void k_wide(FusedBatch batch, Devi
     const int k0 = tl.y;
     const int Re = min(kTileR, d.K - k0);
     const uint32_t tick = d.tick_fixed == 0xFFFFFFFFu ? *d.tick_slot : d.tick_fixed;
-    tile_prologue(V, d, k0, Re, tick, H);
+    tile_prologue(V, d, k0, Re, tick, H, wide_cf_stride<H>() - H);
     // waves w and w + 4 share a SIMD: one forms its operands before its
     // products, the other after
     if (wave < kWideWaves / 2) wide_tile<P, H, NHH, true>(V, w, d, Re * d.T, wave, lane, tid);
