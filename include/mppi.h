@@ -65,7 +65,7 @@ typedef enum mppi_precision {
 typedef enum mppi_path {
   MPPI_PATH_PLAIN = 0,  /* one solve per launch sequence: rollout, SDF, cost, reduce kernels */
   MPPI_PATH_FUSED = 1   /* rollout + SDF + cost fused per tile, batched across solves;
-                           BF16 / BF16X2 / BF16X3 / FP8 with H in {128, 256} and 1-2 hidden H x H layers */
+                           BF16 / BF16X2 / BF16X3 / FP8 with H in {128, 256, 512} and 1-2 hidden H x H layers */
 } mppi_path;
 
 typedef enum mppi_sdf_kind {
@@ -111,11 +111,19 @@ typedef struct mppi_sdf_weights {
   const float* act_scale;    /* FP8 only: n_hidden - 1 static scales of the inputs of hidden layers 2..L */
 } mppi_sdf_weights;
 
-/* One gate: latent code and the cached world pose of its frame (Section IV-B-3:
- * the latent and the camera/gate transform are cached and world points are
- * mapped into that frame before querying the decoder). */
+/* One gate: latent code and the world pose of its frame (Section IV-B-3:
+ * world points are mapped into that frame before querying the decoder).
+ *
+ * Object permanence (Section IV-B-3: while the gate is out of view the last
+ * valid latent and its transform are kept and used): z == NULL marks gate g
+ * of this request as not observed; the engine then uses the latent and frame
+ * of gate g from the latest request of the same instance that observed it
+ * (R and t of this entry are ignored).  The engine keeps that cache per
+ * instance on the device as the folded first-layer term, so an unobserved
+ * gate also skips the fold.  EINVAL when the instance has no observation of
+ * gate g yet, or for the analytic field (which has no latent). */
 typedef struct mppi_gate {
-  const float* z;            /* latent_dim floats */
+  const float* z;            /* latent_dim floats, or NULL: use the instance's cached gate g */
   double R[9];               /* row-major 3x3; columns are the gate axes in the world (x = normal) */
   double t[3];               /* gate origin in the world */
 } mppi_gate;

@@ -58,6 +58,11 @@ struct InstInfo {
   uint64_t id;
   int U_len;      // valid entries of the resident sequence
   bool busy;      // a served solve or a staged batch holds this instance
+  // object permanence: the frame of each gate as last observed (its folded
+  // latent is cached on the device, mppi_engine::instCf)
+  uint32_t seen = 0;             // bit g: gate g observed at least once
+  double R[kMaxG][9] = {};
+  double t[kMaxG][3] = {};
 };
 
 // Deep copy of a request for the served path.
@@ -76,8 +81,9 @@ struct OwnedRequest {
     z.assign((size_t)G * latent, 0.0f);
     gates.assign(r.gates, r.gates + G);
     for (int g = 0; g < G; ++g) {
+      // an unobserved gate (z == NULL) stays NULL
       if (r.gates[g].z) memcpy(&z[(size_t)g * latent], r.gates[g].z, sizeof(float) * latent);
-      gates[g].z = &z[(size_t)g * latent];
+      gates[g].z = r.gates[g].z ? &z[(size_t)g * latent] : nullptr;
     }
     req.gates = gates.data();
   }
@@ -141,6 +147,7 @@ struct mppi_engine {
   DeviceWeights dw{};
   double* instU = nullptr;      // max_instances x T_max x 4
   uint32_t* instTick = nullptr;
+  float* instCf = nullptr;      // MLP: max_instances x G_max x H folded latents (object permanence)
   std::unordered_map<uint64_t, int> inst_map;
   std::vector<InstInfo> inst;
   std::vector<double> hover;    // T_max x 4
@@ -250,15 +257,20 @@ int validate(const mppi_engine* e, const mppi_request* r, double Lo[16]) {
       if (!isfin(r->U_nom[i])) return MPPI_EINVAL;
   if (!r->gates) return MPPI_EINVAL;
   for (int g = 0; g < r->G; ++g) {
+    // an unobserved gate (MLP, z == NULL) takes the instance's cached frame
+    // and latent; whether there is one is checked once the instance's slot
+    // is known (stage)
+    if (!r->gates[g].z) {
+      if (c.sdf_kind != MPPI_SDF_MLP) return MPPI_EINVAL;
+      continue;
+    }
     for (int i = 0; i < 9; ++i)
       if (!isfin(r->gates[g].R[i])) return MPPI_EINVAL;
     for (int i = 0; i < 3; ++i)
       if (!isfin(r->gates[g].t[i])) return MPPI_EINVAL;
-    if (c.sdf_kind == MPPI_SDF_MLP) {
-      if (!r->gates[g].z) return MPPI_EINVAL;
+    if (c.sdf_kind == MPPI_SDF_MLP)
       for (int i = 0; i < c.latent_dim; ++i)
         if (!std::isfinite(r->gates[g].z[i])) return MPPI_EINVAL;
-    }
   }
   return cholesky4(r->Sigma, Lo);
 }
@@ -274,10 +286,25 @@ int acquire_slot(mppi_engine* e, uint64_t id, int* slot) {
   const int s = (int)e->inst.size();
   // a new instance starts from hover with tick 0: every slot of the table is
   // filled with hover and tick 0 at create, so no copy is needed here
-  e->inst.push_back(InstInfo{id, e->cfg.T_max, false});
+  InstInfo info;
+  info.id = id;
+  info.U_len = e->cfg.T_max;
+  info.busy = false;
+  e->inst.push_back(info);
   e->inst_map[id] = s;
   *slot = s;
   return MPPI_OK;
+}
+
+// Every unobserved gate of r (z == NULL) has a cached observation in its
+// instance (object permanence).
+bool gates_cached_ok(const mppi_engine* e, const mppi_request* r) {
+  uint32_t need = 0;
+  for (int g = 0; g < r->G; ++g)
+    if (!r->gates[g].z) need |= 1u << g;
+  if (!need) return true;
+  auto it = e->inst_map.find(r->instance_id);
+  return it != e->inst_map.end() && (e->inst[it->second].seen & need) == need;
 }
 
 int tile_rollouts(const mppi_engine* e, int G) {
@@ -357,9 +384,22 @@ void pack_solve(mppi_engine* e, const mppi_request* r, Solve* s, const double Lo
   float* Rt = (float*)(host + lay.Rt);
   float* bs = (float*)(host + lay.base);
   float* zz = (float*)(host + lay.z);
+  InstInfo& ii = e->inst[s->slot];
+  d.cf_cache = e->instCf ? e->instCf + (size_t)s->slot * c.G_max * H : nullptr;
+  d.fold_cached = 0;
   for (int g = 0; g < G; ++g) {
-    const double* R = r->gates[g].R;
-    const double* tg = r->gates[g].t;
+    const bool observed = r->gates[g].z != nullptr;
+    if (observed) {
+      // this request's observation becomes the instance's cached gate g
+      // (its fold is stored by k_fold when the solve runs)
+      memcpy(ii.R[g], r->gates[g].R, sizeof(ii.R[g]));
+      memcpy(ii.t[g], r->gates[g].t, sizeof(ii.t[g]));
+      ii.seen |= 1u << g;
+    } else {
+      d.fold_cached |= 1u << g;
+    }
+    const double* R = observed ? r->gates[g].R : ii.R[g];
+    const double* tg = observed ? r->gates[g].t : ii.t[g];
     double rt[9];
     for (int i = 0; i < 3; ++i)
       for (int j = 0; j < 3; ++j) rt[i * 3 + j] = R[j * 3 + i];
@@ -376,7 +416,7 @@ void pack_solve(mppi_engine* e, const mppi_request* r, Solve* s, const double Lo
     for (int t = 0; t <= T; ++t)
       for (int i = 0; i < 3; ++i)
         bs[((size_t)g * (T + 1) + t) * 3 + i] = (float)(o[i] + (t * r->dt) * rv[i]);
-    if (c.sdf_kind == MPPI_SDF_MLP) memcpy(zz + (size_t)g * kLatent, r->gates[g].z, sizeof(float) * kLatent);
+    if (c.sdf_kind == MPPI_SDF_MLP && observed) memcpy(zz + (size_t)g * kLatent, r->gates[g].z, sizeof(float) * kLatent);
   }
   float* los = (float*)(host + lay.los);
   for (int t = 0; t < T; ++t) {
@@ -465,6 +505,7 @@ int stage(mppi_engine* e, const std::vector<const mppi_request*>& reqs, bool wan
     s->exports = exports && !e->fused;
     if (rc == MPPI_OK) rc = acquire_slot(e, r->instance_id, &s->slot);
     if (rc == MPPI_OK && e->inst[s->slot].busy) rc = MPPI_EAGAIN;
+    if (rc == MPPI_OK && !gates_cached_ok(e, r)) rc = MPPI_EINVAL;   // a gate never observed
     if (rc == MPPI_OK) {
       s->lay = layout_for(e, r->K, r->T, r->G);
       if (!e->arena.alloc(s->lay.total, &s->off)) rc = MPPI_ENOMEM;
@@ -786,6 +827,7 @@ int mppi_create(const mppi_config* cfg, const mppi_sdf_weights* w, mppi_engine**
     if (e->wmem) hipFree(e->wmem);
     if (e->instU) hipFree(e->instU);
     if (e->instTick) hipFree(e->instTick);
+    if (e->instCf) hipFree(e->instCf);
     return rc;
   };
   hipStream_t s0 = (hipStream_t)c.stream;
@@ -818,6 +860,11 @@ int mppi_create(const mppi_config* cfg, const mppi_sdf_weights* w, mppi_engine**
   if (hipMalloc(&e->instU, sizeof(double) * 4 * c.T_max * nI) != hipSuccess) return bail(MPPI_ENOMEM);
   if (hipMalloc(&e->instTick, sizeof(uint32_t) * nI) != hipSuccess) return bail(MPPI_ENOMEM);
   if (hipMemset(e->instTick, 0, sizeof(uint32_t) * nI) != hipSuccess) return bail(MPPI_EDEVICE);
+  if (c.sdf_kind == MPPI_SDF_MLP) {
+    const size_t cf = sizeof(float) * nI * c.G_max * e->H;
+    if (hipMalloc(&e->instCf, cf) != hipSuccess) return bail(MPPI_ENOMEM);
+    if (hipMemset(e->instCf, 0, cf) != hipSuccess) return bail(MPPI_EDEVICE);
+  }
   e->hover.assign((size_t)4 * c.T_max, 0.0);
   for (int t = 0; t < c.T_max; ++t) e->hover[4 * t] = c.mass * c.gravity;
   {
@@ -855,6 +902,7 @@ int mppi_destroy(mppi_engine* e) {
   if (e->wmem) hipFree(e->wmem);
   if (e->instU) hipFree(e->instU);
   if (e->instTick) hipFree(e->instTick);
+  if (e->instCf) hipFree(e->instCf);
   for (char* p : e->pin)
     if (p) hipHostFree(p);
   delete e;
@@ -1106,6 +1154,29 @@ void scheduler_loop(mppi_engine* e) {
         auto it = e->inst_map.find(id);
         return it != e->inst_map.end() && e->inst[it->second].busy;
       });
+      // a request whose unobserved gate has no cached observation fails on
+      // its own instead of failing the wave it was admitted with
+      for (size_t i = 0; i < adm.size();) {
+        const mppi_request* r = &e->pending[adm[i].ticket].req;
+        if (gates_cached_ok(e, r)) {
+          ++i;
+          continue;
+        }
+        auto s = std::make_unique<Solve>();
+        s->ticket = adm[i].ticket;
+        s->T = r->T;
+        s->res.assign(4 * s->T + RES_SCALARS, 0.0);
+        s->res[4 * s->T + RES_STATUS] = MPPI_EINVAL;
+        s->want_w = s->want_J = false;
+        s->t_submit = e->ticket_submit_ns[adm[i].ticket];
+        s->t_done = now_ns();
+        e->adm->complete(adm[i].footprint);
+        e->stats.failed++;
+        e->done[adm[i].ticket] = std::move(s);
+        e->pending.erase(adm[i].ticket);
+        adm.erase(adm.begin() + i);
+        e->cv.notify_all();
+      }
       if (!adm.empty()) {
         std::vector<bool> used(nstreams + 1, false);
         for (auto& b : e->inflight) used[b.stream_idx] = true;

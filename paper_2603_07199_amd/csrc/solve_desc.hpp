@@ -48,6 +48,9 @@ struct SolveDesc {
   const float* base;     // G x (T+1) x 3: R^T (p0 - t_g) + (t dt) R^T v0
   const float* z;        // G x 64 latent codes
   float* cfold;          // G x H: W1[:, 3:] z_g + b1, computed on the device in FP64
+  float* cf_cache;       // instance's cached folded latents (G_max x H) or NULL
+  uint32_t fold_cached;  // bit g: gate g not observed, take its fold from cf_cache
+  uint32_t pad1;
   const float* los;      // T x 2: wp - p0 - v0 t dt (xy), for eq. 6
   double* U_resident;    // instance slot sequence (T_max x 4) or NULL
   uint32_t* tick_slot;   // instance slot tick

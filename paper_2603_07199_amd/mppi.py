@@ -176,8 +176,10 @@ class _Request:
         gates = (mppi_gate * G)()
         z = np.ascontiguousarray(prob["gate_z"], dtype=np.float32).reshape(G, -1)
         self.keep.append(z)
+        # gate_cached[g] True: gate g not observed, use the instance's cached gate (z = NULL)
+        cached = prob.get("gate_cached")
         for g in range(G):
-            gates[g].z = _fptr(z[g])
+            gates[g].z = None if (cached is not None and cached[g]) else _fptr(z[g])
             gates[g].R[:] = list(np.asarray(prob["gate_R"][g], dtype=np.float64).reshape(9))
             gates[g].t[:] = list(np.asarray(prob["gate_t"][g], dtype=np.float64))
         self.keep.append(gates)

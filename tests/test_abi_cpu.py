@@ -8,6 +8,7 @@ import re
 import shutil
 import subprocess
 
+import numpy as np
 import pytest
 
 from paper_2603_07199_amd import mppi as M
@@ -189,3 +190,19 @@ def test_host_core_logic(tmp_path):
     r = subprocess.run([str(exe)], capture_output=True, text=True)
     assert r.returncode == 0, r.stderr
     assert "HOST OK" in r.stdout
+
+
+def test_request_marshals_unobserved_gates_as_null_latent():
+    """gate_cached[g] → the request's gate g carries a NULL latent pointer
+    (object permanence: the engine uses the instance's cached gate)."""
+    import ctypes
+
+    import scenarios as sc
+    from paper_2603_07199_amd.mppi import _Request
+    prob = sc.make_problem(8, 4, 3, seed=1)
+    r = _Request(dict(prob, gate_cached=[False, True, False])).req
+    assert bool(r.gates[0].z) and not bool(r.gates[1].z) and bool(r.gates[2].z)
+    z0 = ctypes.cast(r.gates[0].z, ctypes.POINTER(ctypes.c_float))
+    assert z0[5] == np.float32(prob["gate_z"][0][5])
+    r_all = _Request(prob).req
+    assert all(bool(r_all.gates[g].z) for g in range(3))
