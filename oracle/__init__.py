@@ -25,14 +25,14 @@ paper (no trained weights exist here; seeded random weights stand in), so
 results that depend on a trained decoder are "parity unpinned".
 """
 from .philox import philox4x64_10, uniforms_from_words, box_muller, control_noise
-from .dynamics import rollout, quat_mul, thrust_axis
+from .dynamics import rollout, rotor_rollout, quat_mul, thrust_axis
 from .sdf import softplus, mlp_concat, mlp_fold, gate_sdf_analytic
 from .precision import bf16_round, e4m3_round, quantise_weights_fp8
 from .mppi import solve, mppi_update, shift_warm_start, hover_sequence
 
 __all__ = [
     "philox4x64_10", "uniforms_from_words", "box_muller", "control_noise",
-    "rollout", "quat_mul", "thrust_axis",
+    "rollout", "rotor_rollout", "quat_mul", "thrust_axis",
     "softplus", "mlp_concat", "mlp_fold", "gate_sdf_analytic",
     "bf16_round", "e4m3_round", "quantise_weights_fp8",
     "solve", "mppi_update", "shift_warm_start", "hover_sequence",

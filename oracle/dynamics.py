@@ -1,8 +1,9 @@
 """Quadrotor rollout f(x, u) for MPPI (oracle side), float64.
 
 Section IV-A uses a standard quadrotor model with state [p, v, q, omega].
-The paper's input is four rotor-thrust rates; here the input is collective
-thrust + body rates, the form of the workloads the library is measured on.
+Two input forms: collective thrust + body rates (the form of the measured
+workloads), and the paper's own four rotor-thrust rates (rotor_rollout
+below), which turn the rotor thrusts and the body rate into state.
 Readings where the paper is silent:
 
 * state layout x = [p(3), q(4) as (w, x, y, z), v(3), omega(3)], world z up;
@@ -86,3 +87,57 @@ def rollout(x0, u, dt, mass, gravity):
         v[:, t + 1] = v[:, t] + a * dt
         q[:, t + 1] = quat_mul(q[:, t], rate_increment(rates, dt))
     return p, q, v
+
+
+# ------------------------------------------------------------ rotor-thrust rates
+#
+# The paper's input (Section IV-A): u = (dT_1, dT_2, dT_3, dT_4)/dt, the
+# rates of the four rotor thrusts (Table I bounds the rates to [-10, 10] N/s,
+# the thrusts to [0, 10] N and the body rate to [-10, 10] rad/s).  The state
+# grows by the four thrusts; the body rate becomes a state driven by the
+# rotor torques.  Readings where the paper is silent (it gives no inertia,
+# arm length or rotor layout):
+#
+# * "X" layout, rotor i at body (x_i, y_i) = a (s_x, s_y) with a = arm / sqrt 2
+#   and (s_x, s_y) = (+,+), (-,-), (+,-), (-,+) for rotors 1..4; rotors 1, 2
+#   and 3, 4 spin in opposite senses, the drag torque of rotor i is
+#   kappa T_i about body z with sign +, +, -, -;
+#   torque tau = sum_i (y_i T_i, -x_i T_i, +/- kappa T_i);
+# * Euler's equations with a diagonal inertia J:
+#   J domega/dt = tau - omega x (J omega);
+# * one step dt, in this order: T_{t+1} = clip(T_t + u_t dt, 0, T_max);
+#   omega_{t+1} = clip(omega_t + dt J^-1 (tau(T_{t+1}) - omega_t x J omega_t),
+#   -omega_max, omega_max) (explicit Euler on the rate, clipped per axis);
+#   then the collective-thrust step above with thrust sum_i T_{t+1,i} and
+#   body rate omega_{t+1}.
+
+
+def rotor_torque(thrusts, arm, kappa):
+    """Body torque (..., 3) of rotor thrusts (..., 4) in the X layout."""
+    a = arm / np.sqrt(2.0)
+    t1, t2, t3, t4 = thrusts[..., 0], thrusts[..., 1], thrusts[..., 2], thrusts[..., 3]
+    return np.stack([a * (t1 - t2 - t3 + t4), a * (-t1 + t2 - t3 + t4), kappa * (t1 + t2 - t3 - t4)], axis=-1)
+
+
+def rotor_inputs(omega0, thrust0, u, dt, model):
+    """Collective thrust and body rate per step (K, T, 4) that the rotor-rate
+    controls u (K, T, 4) produce from body rate omega0 (3,) and rotor thrusts
+    thrust0 (4,)."""
+    K, T = u.shape[0], u.shape[1]
+    J = np.asarray(model["inertia"], dtype=np.float64)
+    thr = np.broadcast_to(np.asarray(thrust0, dtype=np.float64), (K, 4)).copy()
+    w = np.broadcast_to(np.asarray(omega0, dtype=np.float64), (K, 3)).copy()
+    out = np.zeros((K, T, 4))
+    for t in range(T):
+        thr = np.clip(thr + u[:, t] * dt, 0.0, model["thrust_max"])
+        tau = rotor_torque(thr, model["arm_length"], model["yaw_coeff"])
+        w = np.clip(w + dt * (tau - np.cross(w, J * w)) / J, -model["rate_max"], model["rate_max"])
+        out[:, t, 0] = thr.sum(axis=1)
+        out[:, t, 1:4] = w
+    return out
+
+
+def rotor_rollout(x0, thrust0, u, dt, model):
+    """rollout() for rotor-thrust-rate controls u (K, T, 4); x0 carries the
+    initial body rate in x0[10:13], thrust0 the four rotor thrusts."""
+    return rollout(x0, rotor_inputs(x0[10:13], thrust0, u, dt, model), dt, model["mass"], model["gravity"])

@@ -30,7 +30,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .dynamics import rollout
+from .dynamics import rollout, rotor_rollout
 from .philox import control_noise
 from .precision import contract_weights
 from .sdf import gate_sdf_analytic, mlp_concat
@@ -41,10 +41,12 @@ STATUS_OK = 0
 STATUS_ENUMERIC = -5
 
 
-def hover_sequence(T, mass, gravity):
-    """Nominal sequence of a new instance: hover thrust m g, zero body rates."""
+def hover_sequence(T, mass, gravity, rotor=False):
+    """Nominal sequence of a new instance: hover thrust m g, zero body rates
+    (rotor-thrust rates: zero rates, the thrusts stay where they are)."""
     U = np.zeros((T, 4))
-    U[:, 0] = mass * gravity
+    if not rotor:
+        U[:, 0] = mass * gravity
     return U
 
 
@@ -140,7 +142,9 @@ def shift_warm_start(U):
 def solve(prob, weights, model, contract="fp32", sdf_kind="mlp", act_scales=None,
           U_nom=None):
     """One MPPI iteration.  ``weights`` = (W list, b list) float32 as given
-    to the library; ``model`` = dict(mass, gravity, u_lo, u_hi).
+    to the library; ``model`` = dict(mass, gravity, u_lo, u_hi), plus for the
+    rotor-thrust-rate input (kind "rotor") inertia, arm_length, yaw_coeff,
+    thrust_max, rate_max, with the rotor thrusts in ``prob["thrust0"]``.
 
     Returns a dict with U_star (T, 4), u0 (4,), J (K,), w (K,), rho, log_eta,
     ess, status and the intermediates samples (K, T, 4), p_rel (K, T+1, 3),
@@ -148,11 +152,15 @@ def solve(prob, weights, model, contract="fp32", sdf_kind="mlp", act_scales=None
     T = prob["T"]
     if U_nom is None:
         U_nom = prob["U_nom"]
+    rotor = model.get("kind") == "rotor"
     if U_nom is None:
-        U_nom = hover_sequence(T, model["mass"], model["gravity"])
+        U_nom = hover_sequence(T, model["mass"], model["gravity"], rotor=rotor)
     U_nom = np.asarray(U_nom, dtype=np.float64)
     u = sample_controls(prob, model, U_nom)
-    p_rel, q, _ = rollout(prob["x0"], u, prob["dt"], model["mass"], model["gravity"])
+    if rotor:
+        p_rel, q, _ = rotor_rollout(prob["x0"], prob["thrust0"], u, prob["dt"], model)
+    else:
+        p_rel, q, _ = rollout(prob["x0"], u, prob["dt"], model["mass"], model["gravity"])
     s = sdf_values(p_rel, prob, weights, contract, act_scales, sdf_kind)
     J_gate = progress_cost_closed(p_rel, prob["x0"][0:3], prob["wp"])
     J_sdf = np.sum(np.maximum(0.0, prob["d_safe"] - s), axis=1)

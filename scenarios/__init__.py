@@ -32,6 +32,26 @@ MODEL = {
 # Noise covariance diag(sigma^2) for sigma = (2.0 N, 0.5, 0.5, 0.3 rad/s).
 SIGMA_DIAG = np.array([4.0, 0.25, 0.25, 0.09])
 
+# The paper's own input (Section IV-A): rates of the four rotor thrusts.
+# Table I bounds the rates to [-10, 10] N/s, the thrusts to [0, 10] N and the
+# body rate to [-10, 10] rad/s; the paper gives no inertia or geometry, so a
+# 370 g racing quadrotor's are assumed (diagonal inertia, 0.09 m arms, yaw
+# torque 0.016 N m per N of thrust).
+ROTOR_MODEL = {
+    "kind": "rotor",
+    "mass": 0.370,
+    "gravity": 9.81,
+    "u_lo": np.array([-10.0, -10.0, -10.0, -10.0]),
+    "u_hi": np.array([10.0, 10.0, 10.0, 10.0]),
+    "inertia": np.array([1.5e-3, 1.5e-3, 2.6e-3]),
+    "arm_length": 0.09,
+    "yaw_coeff": 0.016,
+    "thrust_max": 10.0,
+    "rate_max": 10.0,
+}
+# Rotor-thrust-rate noise sigma = 4 N/s per rotor.
+ROTOR_SIGMA_DIAG = np.array([16.0, 16.0, 16.0, 16.0])
+
 LATENT_DIM = 64
 
 # Named workloads.  Sizes follow the five benchmark configurations of this
@@ -131,6 +151,22 @@ def make_problem(K, T, G, dt=0.02, rot="haar", start="rest", seed=1, instance_id
         "gate_z": z, "gate_R": R, "gate_t": t,
         "flags": int(flags),
     }
+
+
+def rotor_problem(K, T, G, seed=1, **kw):
+    """A make_problem() request for the rotor-thrust-rate input: rate noise,
+    rotor thrusts near hover (m g / 4 each, +-0.2 N) and, for a moving start,
+    a body rate in [-1, 1] rad/s, drawn from a second stream so that the
+    rest of the problem equals make_problem(K, T, G, seed, ...)."""
+    kw.setdefault("Sigma", np.diag(ROTOR_SIGMA_DIAG))
+    p = make_problem(K, T, G, seed=seed, **kw)
+    rng = np.random.default_rng(seed + 1_000_003)
+    m = ROTOR_MODEL
+    p["thrust0"] = m["mass"] * m["gravity"] / 4.0 + rng.uniform(-0.2, 0.2, size=4)
+    if kw.get("start", "rest") == "moving":
+        p["x0"] = p["x0"].copy()
+        p["x0"][10:13] = rng.uniform(-1.0, 1.0, size=3)
+    return p
 
 
 def config_problem(name, seed, **over):

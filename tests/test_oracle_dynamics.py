@@ -138,3 +138,81 @@ def test_scene_yaw_rotation_leaves_update_unchanged(sdf_kind):
     r2 = solve(p2, (W, b), sc.MODEL, sdf_kind=sdf_kind)
     assert np.allclose(r1["J"], r2["J"], rtol=0, atol=1e-9 * (1 + np.abs(r1["J"]).max()))
     assert np.allclose(r1["U_star"], r2["U_star"], rtol=0, atol=1e-11)
+
+
+# ---------------------------------------------------------- rotor-thrust rates
+from oracle.dynamics import rotor_inputs, rotor_rollout, rotor_torque  # noqa: E402
+
+RM = sc.ROTOR_MODEL
+
+
+def test_rotor_hover_thrusts_hold_position_and_attitude():
+    """Four equal thrusts m g / 4, zero rates, zero body rate: no torque, no
+    acceleration (the rotor form of the hover pin)."""
+    T, dt = 50, 0.02
+    thr = np.full(4, RM["mass"] * RM["gravity"] / 4.0)
+    p, q, v = rotor_rollout(_x0(), thr, np.zeros((2, T, 4)), dt, RM)
+    assert np.max(np.abs(p)) <= 1e-14
+    assert np.max(np.abs(v)) <= 1e-14
+    assert np.allclose(q, [1, 0, 0, 0], atol=0)
+
+
+def test_rotor_torque_layout():
+    """X layout: a differential between rotor pairs gives a pure roll, pitch
+    or yaw torque of the closed-form size."""
+    a, kap = RM["arm_length"] / np.sqrt(2.0), RM["yaw_coeff"]
+    c, d = 1.0, 0.1
+    assert np.allclose(rotor_torque(np.array([c + d, c - d, c - d, c + d]), RM["arm_length"], kap), [4 * a * d, 0, 0])
+    assert np.allclose(rotor_torque(np.array([c - d, c + d, c - d, c + d]), RM["arm_length"], kap), [0, 4 * a * d, 0])
+    assert np.allclose(rotor_torque(np.array([c + d, c + d, c - d, c - d]), RM["arm_length"], kap), [0, 0, 4 * kap * d])
+    assert np.allclose(rotor_torque(np.full(4, 2.0), RM["arm_length"], kap), 0.0, atol=0)
+
+
+def test_rotor_yaw_differential_spins_up_linearly():
+    """Constant yaw torque about a principal axis: no gyroscopic term, the
+    explicit-Euler rate is n dt tau_z / J_z exactly; collective thrust is
+    the sum of the four thrusts."""
+    T, dt, c, d = 20, 0.01, 0.9, 0.05
+    thr = np.array([c + d, c + d, c - d, c - d])
+    inp = rotor_inputs(np.zeros(3), thr, np.zeros((1, T, 4)), dt, RM)
+    n = np.arange(1, T + 1)
+    assert np.allclose(inp[0, :, 3], n * dt * 4 * RM["yaw_coeff"] * d / RM["inertia"][2], rtol=1e-13, atol=0)
+    assert np.max(np.abs(inp[0, :, 1:3])) == 0.0
+    assert np.allclose(inp[0, :, 0], 4 * c, rtol=1e-15)
+
+
+def test_rotor_gyroscopic_term_sign():
+    """Torque-free body spinning about x and z: one Euler step changes the y
+    rate by dt (J_z - J_x) / J_y w_z w_x (the sign of omega x J omega)."""
+    dt, wx, wz = 0.005, 1.5, -2.0
+    thr = np.full(4, 1.0)
+    inp = rotor_inputs(np.array([wx, 0.0, wz]), thr, np.zeros((1, 1, 4)), dt, RM)
+    Jx, Jy, Jz = RM["inertia"]
+    assert np.isclose(inp[0, 0, 2], dt * (Jz - Jx) / Jy * wz * wx, rtol=1e-13, atol=0)
+    assert np.isclose(inp[0, 0, 1], wx, rtol=0, atol=1e-15)      # (J_y - J_z) w_y w_z = 0
+    assert np.isclose(inp[0, 0, 3], wz, rtol=0, atol=1e-15)
+
+
+def test_rotor_thrust_and_rate_limits():
+    """Rates integrate the thrusts and saturate at Table I's bounds; zero
+    thrusts fall freely (the rotor form of the free-fall pin)."""
+    T, dt = 30, 0.05
+    u = np.full((1, T, 4), 10.0)
+    inp = rotor_inputs(np.zeros(3), np.full(4, 8.0), u, dt, RM)
+    assert np.allclose(inp[0, :, 0], np.minimum(4 * (8.0 + 10.0 * dt * np.arange(1, T + 1)), 40.0))
+    p, q, v = rotor_rollout(_x0(v=(1.0, 0, 0)), np.zeros(4), np.full((1, T, 4), -10.0), dt, RM)
+    t = np.arange(T + 1) * dt
+    assert np.max(np.abs(p[0, :, 2] + 0.5 * G * t ** 2)) <= 1e-12
+    assert np.max(np.abs(p[0, :, 0] - t)) <= 1e-12
+    big = rotor_inputs(np.array([0.0, 0.0, 9.99]), np.array([0.0, 0.0, 10.0, 10.0]), np.zeros((1, 5, 4)), 0.1, RM)
+    assert np.all(np.abs(big[0, :, 1:4]) <= RM["rate_max"])
+
+
+def test_rotor_solve_zero_noise_returns_nominal():
+    """MPPI invariant under the rotor input: zero noise gives back the
+    nominal rate sequence."""
+    prob = sc.rotor_problem(16, 10, 1, seed=3, start="moving", Sigma=np.zeros((4, 4)))
+    W, b = sc.xavier_weights((67, 32, 32, 1), seed=1)
+    U = np.random.default_rng(0).uniform(-2, 2, size=(10, 4))
+    out = solve(prob, (W, b), RM, U_nom=U)
+    assert np.allclose(out["U_star"], U, rtol=0, atol=1e-12)
