@@ -17,7 +17,10 @@
  *    K horizon steps);
  *  - state x = [p(3), q(4) as (w, x, y, z), v(3), omega(3)], world z up,
  *    Hamilton quaternions body -> world, thrust along body +z;
- *  - control u = [collective thrust (N), body rates wx, wy, wz (rad/s)];
+ *  - control u = [collective thrust (N), body rates wx, wy, wz (rad/s)]
+ *    (MPPI_DYN_CTBR), or the paper's own input, the rates of the four rotor
+ *    thrusts (N/s) with the thrusts and the body rate as state
+ *    (MPPI_DYN_ROTOR_RATES, see mppi_dynamics);
  *  - noise: Philox4x64-10, counter (k, t, instance_id, tick), key (seed, 0),
  *    23-bit uniforms and Box-Muller, delta u = L n with L L^T = Sigma;
  *  - the SDF is queried at the T predicted positions p_1..p_T (flag
@@ -73,6 +76,18 @@ typedef enum mppi_sdf_kind {
   MPPI_SDF_ANALYTIC = 1   /* guidance field s = c + |x| tan(alpha) - max(|y|,|z|) (eqs. 1-2) */
 } mppi_sdf_kind;
 
+/* Vehicle model (Section IV-A).  ROTOR_RATES: u = (dT_1 .. dT_4)/dt; rotor i
+ * sits at body (x_i, y_i) = arm/sqrt(2) (s_x, s_y), (s_x, s_y) = (+,+), (-,-),
+ * (+,-), (-,+) for i = 1..4, drag torque +/- yaw_coeff T_i about body z with
+ * signs +, +, -, -; per step: T <- clip(T + u dt, 0, thrust_max),
+ * omega <- clip(omega + dt J^-1 (tau(T) - omega x J omega), +-rate_max) with
+ * J = diag(inertia), then the CTBR step with thrust sum T_i and body rate
+ * omega.  The rotor thrusts at x0 come with each request (thrust0). */
+typedef enum mppi_dynamics {
+  MPPI_DYN_CTBR = 0,         /* collective thrust + body rates (rate follows the command) */
+  MPPI_DYN_ROTOR_RATES = 1   /* rotor-thrust rates; state adds the 4 thrusts and the body rate */
+} mppi_dynamics;
+
 /* Config flags. */
 #define MPPI_CFG_TIMING (1u << 0)  /* record per-kernel HIP event times (see mppi_get_stats) */
 
@@ -99,6 +114,11 @@ typedef struct mppi_config {
   void* stream;              /* hipStream_t for the blocking path, or NULL: engine creates one */
   void* device_pool;         /* optional caller-owned device memory for per-solve buffers */
   uint64_t device_pool_bytes;
+  int32_t dynamics;          /* mppi_dynamics */
+  int32_t pad_dyn;
+  /* MPPI_DYN_ROTOR_RATES only (all > 0): principal inertia (kg m^2), arm
+   * length (m), yaw drag torque per thrust (m), thrust and body-rate bounds */
+  double inertia[3], arm_length, yaw_coeff, thrust_max, rate_max;
 } mppi_config;
 
 /* Decoder weights, row-major float32 as a (n_out x n_in) matrix per layer
@@ -149,6 +169,7 @@ typedef struct mppi_request {
   double Q_gate, Q_vis, Q_sdf, d_safe, R_u;  /* cost weights (eq. 9) and clearance (eq. 7) */
   double wp[3];              /* target waypoint p_wp (eq. 5); also the gate centre for eq. 6 */
   const mppi_gate* gates;    /* G gates */
+  double thrust0[4];         /* MPPI_DYN_ROTOR_RATES: rotor thrusts at x0, in [0, thrust_max]; x0[10..12] is the body rate */
 } mppi_request;
 
 /* Result of one solve (caller-owned buffers). */
@@ -182,7 +203,7 @@ int mppi_destroy(mppi_engine* engine);
 
 /* One blocking solve.  EINVAL: lambda <= 0 or non-finite, Sigma not PSD,
  * K/T/G outside [1, max], non-finite x0 or U_nom, |q| not within 1e-6 of 1,
- * NULL U_star/gates.  ENUMERIC: every cost non-finite (U_star = nominal,
+ * NULL U_star/gates, rotor thrusts outside [0, thrust_max].  ENUMERIC: every cost non-finite (U_star = nominal,
  * the resident warm start is kept).  Uses the engine's own stream. */
 int mppi_step(mppi_engine* engine, const mppi_request* request, mppi_result* result);
 

@@ -115,6 +115,53 @@ __device__ __forceinline__ void quad_step(RolloutState& s, const float u[4], flo
   s.q[3] = w * rz + x * ry - y * rx + z * rw;
 }
 
+// Rotor-thrust-rate input (Section IV-A): the four rotor thrusts and the
+// body rate are state.  One step: thrusts integrate their rates and are
+// clipped to [0, thrust_max]; the body rate takes an explicit Euler step of
+// J domega/dt = tau - omega x J omega (X layout, torques from the new
+// thrusts) and is clipped per axis; out = (collective thrust, body rate) for
+// quad_step.
+struct RotorState {
+  float thr[4], w[3];
+};
+
+__device__ __forceinline__ void rotor_init(RotorState& r, const SolveDesc& d) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) r.thr[i] = d.thrust0[i];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) r.w[i] = d.w0[i];
+}
+
+__device__ __forceinline__ void rotor_step(RotorState& r, const float udot[4], const SolveDesc& d, float out[4]) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) r.thr[i] = fminf(fmaxf(fmaf(udot[i], d.dt, r.thr[i]), 0.0f), d.thrust_max);
+  const float t1 = r.thr[0], t2 = r.thr[1], t3 = r.thr[2], t4 = r.thr[3];
+  const float tau[3] = {d.rot_a * ((t1 - t2) + (t4 - t3)), d.rot_a * ((t2 - t1) + (t4 - t3)),
+                        d.rot_kappa * ((t1 + t2) - (t3 + t4))};
+  const float Jw[3] = {d.Jd[0] * r.w[0], d.Jd[1] * r.w[1], d.Jd[2] * r.w[2]};
+  const float gyro[3] = {r.w[1] * Jw[2] - r.w[2] * Jw[1], r.w[2] * Jw[0] - r.w[0] * Jw[2],
+                         r.w[0] * Jw[1] - r.w[1] * Jw[0]};
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+    r.w[i] = fminf(fmaxf(fmaf(d.dt * d.Jinv[i], tau[i] - gyro[i], r.w[i]), -d.rate_max), d.rate_max);
+  out[0] = (t1 + t2) + (t3 + t4);
+  out[1] = r.w[0];
+  out[2] = r.w[1];
+  out[3] = r.w[2];
+}
+
+// One rollout step under the configured input: rs is used only for the
+// rotor-thrust-rate input.
+__device__ __forceinline__ void vehicle_step(RolloutState& s, RotorState& rs, const float u[4], const SolveDesc& d) {
+  if (d.dyn == 1) {
+    float uc[4];
+    rotor_step(rs, u, d, uc);
+    quad_step(s, uc, d.dt, d.inv_mass, d.gravity);
+  } else {
+    quad_step(s, u, d.dt, d.inv_mass, d.gravity);
+  }
+}
+
 // 1 - cos(psi - psi_los) for the yaw psi of q and the bearing of (lx, ly)
 // (eq. 6); atan2(0, 0) = 0 conventions for degenerate vectors.
 __device__ __forceinline__ float alignment_term(const float q[4], float lx, float ly) {

@@ -243,6 +243,9 @@ int validate(const mppi_engine* e, const mppi_request* r, double Lo[16]) {
   if (!isfin(r->lambda) || r->lambda <= 0.0) return MPPI_EINVAL;
   for (int i = 0; i < 13; ++i)
     if (!isfin(r->x0[i])) return MPPI_EINVAL;
+  if (c.dynamics == MPPI_DYN_ROTOR_RATES)
+    for (int i = 0; i < 4; ++i)
+      if (!(r->thrust0[i] >= 0.0 && r->thrust0[i] <= c.thrust_max)) return MPPI_EINVAL;
   const double qn = sqrt(r->x0[3] * r->x0[3] + r->x0[4] * r->x0[4] + r->x0[5] * r->x0[5] +
                          r->x0[6] * r->x0[6]);
   if (fabs(qn - 1.0) > 1e-6) return MPPI_EINVAL;
@@ -370,7 +373,20 @@ void pack_solve(mppi_engine* e, const mppi_request* r, Solve* s, const double Lo
                     2.0 * (vt[0] * ev[0] + vt[1] * ev[1] + vt[2] * ev[2]);
   d.C0 = (qg == 0.0 || c0 == 0.0) ? 0.0 : qg * c0;
   s->C0 = d.C0;
-  d.hover[0] = c.mass * c.gravity;
+  d.hover[0] = c.dynamics == MPPI_DYN_ROTOR_RATES ? 0.0 : c.mass * c.gravity;
+  d.dyn = c.dynamics;
+  if (c.dynamics == MPPI_DYN_ROTOR_RATES) {
+    d.rot_a = (float)(c.arm_length / std::sqrt(2.0));
+    d.rot_kappa = (float)c.yaw_coeff;
+    d.thrust_max = (float)c.thrust_max;
+    d.rate_max = (float)c.rate_max;
+    for (int i = 0; i < 3; ++i) {
+      d.Jd[i] = (float)c.inertia[i];
+      d.Jinv[i] = (float)(1.0 / c.inertia[i]);
+      d.w0[i] = (float)r->x0[10 + i];
+    }
+    for (int i = 0; i < 4; ++i) d.thrust0[i] = (float)r->thrust0[i];
+  }
   if (r->U_nom) {
     memcpy(host + lay.U, r->U_nom, sizeof(double) * 4 * T);
     d.U_src = (const double*)(base + lay.U);
@@ -804,6 +820,14 @@ int mppi_create(const mppi_config* cfg, const mppi_sdf_weights* w, mppi_engine**
   for (int i = 0; i < 4; ++i)
     if (!isfin(c.u_lo[i]) || !isfin(c.u_hi[i]) || c.u_lo[i] > c.u_hi[i]) return MPPI_EINVAL;
   if (!c.device_pool && c.hbm_budget_bytes == 0) return MPPI_EINVAL;
+  if (c.dynamics != MPPI_DYN_CTBR && c.dynamics != MPPI_DYN_ROTOR_RATES) return MPPI_EINVAL;
+  if (c.dynamics == MPPI_DYN_ROTOR_RATES) {
+    for (int i = 0; i < 3; ++i)
+      if (!(c.inertia[i] > 0.0) || !isfin(c.inertia[i])) return MPPI_EINVAL;
+    if (!(c.arm_length > 0.0) || !isfin(c.arm_length) || !isfin(c.yaw_coeff)) return MPPI_EINVAL;
+    if (!(c.thrust_max > 0.0) || !isfin(c.thrust_max) || !(c.rate_max > 0.0) || !isfin(c.rate_max))
+      return MPPI_EINVAL;
+  }
 
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || c.device < 0 || ndev <= c.device) return MPPI_EDEVICE;
@@ -866,7 +890,10 @@ int mppi_create(const mppi_config* cfg, const mppi_sdf_weights* w, mppi_engine**
     if (hipMemset(e->instCf, 0, cf) != hipSuccess) return bail(MPPI_EDEVICE);
   }
   e->hover.assign((size_t)4 * c.T_max, 0.0);
-  for (int t = 0; t < c.T_max; ++t) e->hover[4 * t] = c.mass * c.gravity;
+  // a new instance starts from hover: thrust m g at zero body rate, or zero
+  // rotor-thrust rates (the thrusts stay where the request puts them)
+  if (c.dynamics != MPPI_DYN_ROTOR_RATES)
+    for (int t = 0; t < c.T_max; ++t) e->hover[4 * t] = c.mass * c.gravity;
   {
     // every instance slot starts at hover
     std::vector<double> all(e->hover.size() * nI);

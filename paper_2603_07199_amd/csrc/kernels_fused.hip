@@ -310,6 +310,44 @@ __device__ __forceinline__ void tile_noise(const Views& V, const SolveDesc& d, i
   }
 }
 
+// Dynamics of this lane's rollout (lanes < Re): positions into V.dp and the
+// rollout's progress + control + alignment cost into V.jl.  ROTOR: the
+// rotor-thrust-rate input (a separate instance, so that the collective-thrust
+// loop carries no rotor state).
+template <bool ROTOR>
+__device__ __forceinline__ void tile_dynamics(const Views& V, const SolveDesc& d, int tid) {
+  const int T = d.T;
+  RolloutState s;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) { s.dp[i] = 0.0f; s.dv[i] = 0.0f; }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) s.q[i] = d.q0[i];
+  RotorState rs;
+  if constexpr (ROTOR) rotor_init(rs, d);
+  float* dpk = V.dp + 3 * tid * (T + 1);
+  dpk[0] = dpk[1] = dpk[2] = 0.0f;
+  float Jc = 0.0f, Jv = 0.0f;
+  for (int t = 0; t < T; ++t) {
+    const float4 uu = *(const float4*)(V.samp + 4 * (tid * T + t));
+    const float u[4] = {uu.x, uu.y, uu.z, uu.w};
+    Jc = fmaf(u[0], u[0], fmaf(u[1], u[1], fmaf(u[2], u[2], fmaf(u[3], u[3], Jc))));
+    if (d.Q_vis != 0.0f) Jv += alignment_term(s.q, V.los[2 * t] - s.dp[0], V.los[2 * t + 1] - s.dp[1]);
+    if constexpr (ROTOR) {
+      float uc[4];
+      rotor_step(rs, u, d, uc);
+      quad_step(s, uc, d.dt, d.inv_mass, d.gravity);
+    } else {
+      quad_step(s, u, d.dt, d.inv_mass, d.gravity);
+    }
+    dpk[3 * (t + 1) + 0] = s.dp[0];
+    dpk[3 * (t + 1) + 1] = s.dp[1];
+    dpk[3 * (t + 1) + 2] = s.dp[2];
+  }
+  const float Jg = s.dp[0] * s.dp[0] + s.dp[1] * s.dp[1] + s.dp[2] * s.dp[2] +
+                   2.0f * (s.dp[0] * d.fprog[0] + s.dp[1] * d.fprog[1] + s.dp[2] * d.fprog[2]);
+  V.jl[tid] = d.Q_gate * Jg + d.R_u * Jc + d.Q_vis * Jv;
+}
+
 // Per-tile tables, noise and dynamics (all threads of the workgroup call it).
 // The folded latent rows go to V.cf with row stride H + cf_pad.
 __device__ void tile_prologue(const Views& V, const SolveDesc& d, int k0, int Re, uint32_t tick, int H,
@@ -324,27 +362,8 @@ __device__ void tile_prologue(const Views& V, const SolveDesc& d, int k0, int Re
   __syncthreads();
   // dynamics: one lane per rollout
   if (tid < Re) {
-    RolloutState s;
-#pragma unroll
-    for (int i = 0; i < 3; ++i) { s.dp[i] = 0.0f; s.dv[i] = 0.0f; }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) s.q[i] = d.q0[i];
-    float* dpk = V.dp + 3 * tid * (T + 1);
-    dpk[0] = dpk[1] = dpk[2] = 0.0f;
-    float Jc = 0.0f, Jv = 0.0f;
-    for (int t = 0; t < T; ++t) {
-      const float4 uu = *(const float4*)(V.samp + 4 * (tid * T + t));
-      const float u[4] = {uu.x, uu.y, uu.z, uu.w};
-      Jc = fmaf(u[0], u[0], fmaf(u[1], u[1], fmaf(u[2], u[2], fmaf(u[3], u[3], Jc))));
-      if (d.Q_vis != 0.0f) Jv += alignment_term(s.q, V.los[2 * t] - s.dp[0], V.los[2 * t + 1] - s.dp[1]);
-      quad_step(s, u, d.dt, d.inv_mass, d.gravity);
-      dpk[3 * (t + 1) + 0] = s.dp[0];
-      dpk[3 * (t + 1) + 1] = s.dp[1];
-      dpk[3 * (t + 1) + 2] = s.dp[2];
-    }
-    const float Jg = s.dp[0] * s.dp[0] + s.dp[1] * s.dp[1] + s.dp[2] * s.dp[2] +
-                     2.0f * (s.dp[0] * d.fprog[0] + s.dp[1] * d.fprog[1] + s.dp[2] * d.fprog[2]);
-    V.jl[tid] = d.Q_gate * Jg + d.R_u * Jc + d.Q_vis * Jv;
+    if (d.dyn == 1) tile_dynamics<true>(V, d, tid);
+    else tile_dynamics<false>(V, d, tid);
   }
   __syncthreads();
 }

@@ -69,6 +69,8 @@ __global__ __launch_bounds__(256) void k_rollout(const SolveDesc* __restrict__ d
   for (int i = 0; i < 3; ++i) { s.dp[i] = 0.0f; s.dv[i] = 0.0f; }
 #pragma unroll
   for (int i = 0; i < 4; ++i) s.q[i] = d.q0[i];
+  RotorState rs;
+  rotor_init(rs, d);
   const size_t TK = (size_t)T * K, T1K = (size_t)(T + 1) * K;
   for (int c = 0; c < 3; ++c) d.pos[c * T1K + k] = 0.0f;
   float Jc = 0.0f, Jv = 0.0f;
@@ -80,7 +82,7 @@ __global__ __launch_bounds__(256) void k_rollout(const SolveDesc* __restrict__ d
     Jc = fmaf(u[0], u[0], fmaf(u[1], u[1], fmaf(u[2], u[2], fmaf(u[3], u[3], Jc))));
     if (d.Q_vis != 0.0f)
       Jv += alignment_term(s.q, d.los[2 * t] - s.dp[0], d.los[2 * t + 1] - s.dp[1]);
-    quad_step(s, u, d.dt, d.inv_mass, d.gravity);
+    vehicle_step(s, rs, u, d);
 #pragma unroll
     for (int c = 0; c < 3; ++c) d.pos[c * T1K + (size_t)(t + 1) * K + k] = s.dp[c];
   }

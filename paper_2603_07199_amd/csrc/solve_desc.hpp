@@ -33,6 +33,13 @@ struct SolveDesc {
   // dynamics (float32 copies of float64 inputs)
   float dt, inv_mass, gravity, pad0;
   float q0[4];
+  // rotor-thrust-rate input (dyn == 1): X-layout lever a = arm / sqrt 2, yaw
+  // drag per thrust, bounds, principal inertia and its inverse, the rotor
+  // thrusts and body rate at x0
+  int32_t dyn;
+  float rot_a, rot_kappa, thrust_max, rate_max;
+  float Jd[3], Jinv[3];
+  float thrust0[4], w0[3];
   float L[16];           // lower-triangular noise factor, row-major
   float u_lo[4], u_hi[4];
   // costs

@@ -44,6 +44,9 @@ class mppi_config(C.Structure):
         ("u_lo", C.c_double * 4), ("u_hi", C.c_double * 4),
         ("sdf_c", C.c_double), ("sdf_tan_alpha", C.c_double),
         ("stream", C.c_void_p), ("device_pool", C.c_void_p), ("device_pool_bytes", C.c_uint64),
+        ("dynamics", C.c_int32), ("pad_dyn", C.c_int32),
+        ("inertia", C.c_double * 3), ("arm_length", C.c_double), ("yaw_coeff", C.c_double),
+        ("thrust_max", C.c_double), ("rate_max", C.c_double),
     ]
 
 
@@ -64,7 +67,7 @@ class mppi_request(C.Structure):
         ("Sigma", C.c_double * 16), ("lambda_", C.c_double),
         ("Q_gate", C.c_double), ("Q_vis", C.c_double), ("Q_sdf", C.c_double),
         ("d_safe", C.c_double), ("R_u", C.c_double), ("wp", C.c_double * 3),
-        ("gates", C.POINTER(mppi_gate)),
+        ("gates", C.POINTER(mppi_gate)), ("thrust0", C.c_double * 4),
     ]
 
 
@@ -172,6 +175,8 @@ class _Request:
         r.Q_gate, r.Q_vis, r.Q_sdf = float(prob["Q_gate"]), float(prob["Q_vis"]), float(prob["Q_sdf"])
         r.d_safe, r.R_u = float(prob["d_safe"]), float(prob["R_u"])
         r.wp[:] = list(np.asarray(prob["wp"], dtype=np.float64))
+        if prob.get("thrust0") is not None:
+            r.thrust0[:] = list(np.asarray(prob["thrust0"], dtype=np.float64))
         G = r.G
         gates = (mppi_gate * G)()
         z = np.ascontiguousarray(prob["gate_z"], dtype=np.float32).reshape(G, -1)
@@ -227,7 +232,7 @@ def mppi_create(config, weights):
     lib = load_library()
     c = mppi_config()
     for k, v in config.items():
-        if k in ("u_lo", "u_hi"):
+        if k in ("u_lo", "u_hi", "inertia"):
             getattr(c, k)[:] = [float(x) for x in v]
         else:
             setattr(c, k, v)
@@ -348,6 +353,11 @@ def default_config(model, K_max=8192, T_max=64, G_max=8, hidden=256, n_hidden=3,
         "u_lo": list(model["u_lo"]), "u_hi": list(model["u_hi"]),
         "sdf_c": 0.5, "sdf_tan_alpha": 0.5,
         "stream": stream, "device_pool": device_pool, "device_pool_bytes": int(device_pool_bytes),
+        # vehicle model: model["kind"] == "rotor" selects the rotor-thrust-rate input
+        "dynamics": 1 if model.get("kind") == "rotor" else 0,
+        "inertia": list(model.get("inertia", (0.0, 0.0, 0.0))),
+        "arm_length": float(model.get("arm_length", 0.0)), "yaw_coeff": float(model.get("yaw_coeff", 0.0)),
+        "thrust_max": float(model.get("thrust_max", 0.0)), "rate_max": float(model.get("rate_max", 0.0)),
     }
 
 
