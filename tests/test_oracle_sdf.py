@@ -83,3 +83,57 @@ def test_mlp_input_order_is_coordinates_then_latent():
     s2 = mlp_concat(pg, np.full(64, 9.0), W, b)
     assert s1 == s2
     assert np.isclose(s1[0], 4 * np.log1p(np.exp(np.log1p(np.exp(2.0)))))
+
+
+# ------------------------------------------------------ positional encoding
+from oracle.sdf import positional_encoding, pe_freqs_of  # noqa: E402
+
+
+def test_positional_encoding_hand_values():
+    """Features at points where sin / cos of multiples of pi are known."""
+    p = np.array([[0.25, 0.5, -1.0]])
+    f = positional_encoding(p, 2)[0]
+    r2 = np.sqrt(0.5)
+    expect = [0.25, 0.5, -1.0,
+              r2, 1.0, 0.0, r2, 0.0, -1.0,          # sin(pi p), cos(pi p)
+              1.0, 0.0, 0.0, 0.0, -1.0, 1.0]        # sin(2 pi p), cos(2 pi p)
+    assert np.allclose(f, expect, atol=1e-15)
+    assert positional_encoding(p, 0).shape == (1, 3)
+
+
+def test_encoded_decoder_is_periodic_without_raw_coordinates():
+    """With the raw-coordinate columns zeroed the encoded decoder depends on
+    p only through sin / cos(2^k pi p): period 2 in every coordinate, and not
+    period 1 (the k = 0 band has period 2)."""
+    F = 3
+    W, b = sc.xavier_weights((3 + 6 * F + 64, 32, 32, 1), seed=2, bias_scale=0.1)
+    W = [w.astype(np.float64) for w in W]
+    b = [v.astype(np.float64) for v in b]
+    W[0][:, 0:3] = 0.0
+    z = np.random.default_rng(1).standard_normal(64)
+    p = np.random.default_rng(2).uniform(-3, 3, size=(50, 3))
+    s0 = mlp_concat(p, z, W, b)
+    for shift in (np.array([2.0, 0, 0]), np.array([0, -2.0, 0]), np.array([0, 0, 4.0])):
+        assert np.allclose(mlp_concat(p + shift, z, W, b), s0, atol=1e-12)
+    assert not np.allclose(mlp_concat(p + np.array([1.0, 0, 0]), z, W, b), s0, atol=1e-6)
+
+
+def test_encoded_decoder_fold_and_concat_agree_and_width():
+    F = 2
+    W, b = sc.xavier_weights((3 + 6 * F + 64, 24, 24, 24, 1), seed=5, bias_scale=0.2)
+    W = [w.astype(np.float64) for w in W]
+    b = [v.astype(np.float64) for v in b]
+    assert pe_freqs_of(W[0], 64) == F
+    z = np.random.default_rng(3).standard_normal(64)
+    p = np.random.default_rng(4).uniform(-6, 6, size=(40, 3))
+    assert np.allclose(mlp_fold(p, z, W, b), mlp_concat(p, z, W, b), rtol=1e-13, atol=1e-13)
+    # the same network through torch in float64 on the explicit features
+    x = np.concatenate([positional_encoding(p, F), np.broadcast_to(z, (40, 64))], axis=1)
+    h = torch.tensor(x)
+    for l in range(len(W)):
+        h = h @ torch.tensor(W[l]).T + torch.tensor(b[l])
+        if l + 1 < len(W):
+            h = torch.nn.functional.softplus(h)
+    assert np.allclose(mlp_concat(p, z, W, b), h[:, 0].numpy(), rtol=1e-13, atol=1e-13)
+    with pytest.raises(ValueError):
+        pe_freqs_of(np.zeros((4, 3 + 5 + 64)), 64)
