@@ -48,15 +48,21 @@ LAYERS = (67, 256, 256, 256, 1)
 K_, T_, G_ = 4096, 50, 4
 
 
-def _set_workload(name):
-    global CFG, LAYERS, K_, T_, G_
+PE_FREQS = 0   # --pe-freqs: the decoder reads PE(p) with this many frequencies
+
+
+def _set_workload(name, pe_freqs=0):
+    global CFG, LAYERS, K_, T_, G_, PE_FREQS
     CFG = WORKLOADS[name][0]
     c = sc.CONFIGS[CFG]
     LAYERS, K_, T_, G_ = tuple(c["layers"]), c["K"], c["T"], c["G"]
+    PE_FREQS = int(pe_freqs)
+    LAYERS = (LAYERS[0] + 6 * PE_FREQS,) + LAYERS[1:]
 
 
 def _workload_str():
-    return f"MPPI solve K={K_} T={T_} dt=0.02 G={G_} decoder " + "-".join(str(x) for x in LAYERS)
+    pe = f", PE with {PE_FREQS} frequencies" if PE_FREQS else ""
+    return f"MPPI solve K={K_} T={T_} dt=0.02 G={G_} decoder " + "-".join(str(x) for x in LAYERS) + pe
 KERNEL_SOURCES = {"plain": "kernels_plain.hip", "fused": "kernels_fused.hip"}
 
 
@@ -110,11 +116,11 @@ def _traffic(path, precision, launches_queries):
 
 
 def run_leg(M, path, precision, batch, steps, warmup):
-    W, b = sc.config_weights(CFG)
+    W, b = sc.xavier_weights(LAYERS, seed=0)
     probs = _problems(batch, M)
     eng = M.Engine((W, b), sc.MODEL, K_max=K_, T_max=T_, G_max=G_, hidden=LAYERS[1],
                    n_hidden=len(LAYERS) - 2, precision=precision, path=path,
-                   budget=8 << 30, timing=True, max_instances=max(64, batch))
+                   budget=8 << 30, timing=True, max_instances=max(64, batch), pe_freqs=PE_FREQS)
     bt = eng.batch(probs)
     for _ in range(warmup):
         bt.run()
@@ -243,7 +249,7 @@ def cpu_baseline():
     import torch
 
     import oracle
-    W, b = sc.config_weights(CFG)
+    W, b = sc.xavier_weights(LAYERS, seed=0)
     prob = sc.config_problem(CFG, 1)
     t0 = time.perf_counter()
     oracle.solve(prob, (W, b), sc.MODEL)
@@ -282,6 +288,8 @@ def main():
     ap.add_argument("--precision", default="bf16x3", choices=["fp32", "bf16", "bf16x2", "bf16x3", "fp8"])
     ap.add_argument("--batch", type=int, default=0, help="solves per step (default: 1, fleet: 1024)")
     ap.add_argument("--workload", default="paper", choices=sorted(WORKLOADS))
+    ap.add_argument("--pe-freqs", type=int, default=0,
+                    help="decoder with the positional encoding of the query point (F frequencies)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
     ap.add_argument("--no-served", action="store_true")
@@ -294,7 +302,7 @@ def main():
         print("bench.py measures one GPU only: the library runs every solve on one GPU "
               "and shards nothing across GPUs; run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
-    _set_workload(args.workload)
+    _set_workload(args.workload, args.pe_freqs)
     if args.batch <= 0:
         args.batch = WORKLOADS[args.workload][1]
     if args.precision == "fp8":
@@ -346,7 +354,7 @@ def main():
         out["fp32_plain"] = {"rollout_steps_per_s": ref["rollout_steps_per_s"],
                              "ms_per_step": ref["ms_per_step"],
                              "speedup": main_leg["rollout_steps_per_s"] / ref["rollout_steps_per_s"]}
-    if not args.no_served and args.path == "fused" and args.workload == "paper":
+    if not args.no_served and args.path == "fused" and args.workload == "paper" and not args.pe_freqs:
         out["served"] = served_leg(M, args.precision, args.served_requests)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()

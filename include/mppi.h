@@ -115,15 +115,18 @@ typedef struct mppi_config {
   void* device_pool;         /* optional caller-owned device memory for per-solve buffers */
   uint64_t device_pool_bytes;
   int32_t dynamics;          /* mppi_dynamics */
-  int32_t pad_dyn;
+  int32_t pe_freqs;          /* F in [0, 8]: the decoder reads PE(p) = [p, sin(2^k pi p), cos(2^k pi p), k < F]
+                                (Section III-B PE; 0 = raw coordinates); plain path, or fused with H <= 256 */
   /* MPPI_DYN_ROTOR_RATES only (all > 0): principal inertia (kg m^2), arm
    * length (m), yaw drag torque per thrust (m), thrust and body-rate bounds */
   double inertia[3], arm_length, yaw_coeff, thrust_max, rate_max;
 } mppi_config;
 
 /* Decoder weights, row-major float32 as a (n_out x n_in) matrix per layer
- * l = 0..n_hidden; layer 0 has n_in = 3 + latent_dim with the gate-frame
- * coordinates in columns 0..2 and the latent code in columns 3..
+ * l = 0..n_hidden; layer 0 has n_in = 3 + 6 pe_freqs + latent_dim: the
+ * gate-frame coordinates in columns 0..2, then for k = 0 .. pe_freqs-1 the
+ * blocks sin(2^k pi p) (x, y, z) and cos(2^k pi p) (x, y, z), then the
+ * latent code.
  * The library copies, quantises and packs them once in mppi_create. */
 typedef struct mppi_sdf_weights {
   const float* const* W;     /* n_hidden + 1 pointers */

@@ -174,6 +174,22 @@ __device__ __forceinline__ float alignment_term(const float q[4], float lx, floa
   return 1.0f - (hx * lx + hy * ly) / (hn * ln);
 }
 
+// ---------------------------------------------------------------- positional encoding
+// Feature f of PE(p), the encoded query point of the decoder's input
+// (Section III-B): f < 3 the coordinates, then for k < F the blocks
+// sin(2^k pi p) and cos(2^k pi p) over (x, y, z); 0 past the last feature.
+// 2^k p is exact in float and sincospif reduces its argument exactly.
+__device__ __forceinline__ float pe_feature(int f, float px, float py, float pz, int F) {
+  if (f < 3) return f == 0 ? px : (f == 1 ? py : pz);
+  const int j = f - 3;
+  if (j >= 6 * F) return 0.0f;
+  const int k = j / 6, r = j - 6 * k, c = r < 3 ? r : r - 3;
+  const float v = ldexpf(c == 0 ? px : (c == 1 ? py : pz), k);
+  float sn, cs;
+  sincospif(v, &sn, &cs);
+  return r < 3 ? sn : cs;
+}
+
 // ---------------------------------------------------------------- activations
 // softplus(x) = log(1 + e^x) = max(x, 0) + log1p(e^-|x|): accurate form.
 __device__ __forceinline__ float softplus_accurate(float x) {

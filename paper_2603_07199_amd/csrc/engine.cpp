@@ -696,6 +696,9 @@ void add_time(mppi_engine* e, hipEvent_t a, hipEvent_t b, bool sdf) {
 int upload_weights(mppi_engine* e, const mppi_sdf_weights* w) {
   const int H = e->H, L = e->L, D = e->cfg.latent_dim;
   const int nh = std::max(L - 1, 1);  // hidden H x H layers
+  const int NF = 3 + 6 * e->cfg.pe_freqs;   // encoded-point columns of layer 0
+  const int KQ = e->cfg.pe_freqs > 0 ? (NF + 3) / 4 : 0;
+  std::vector<float> w1pe((size_t)H * 4 * KQ, 0.0f);
   const bool mlp = e->cfg.sdf_kind == MPPI_SDF_MLP;
   std::vector<float> w1p((size_t)H * 4, 0.0f), hbias((size_t)nh * H, 0.0f), wout(H, 0.0f);
   std::vector<double> w0lat((size_t)H * D, 0.0), b0(H, 0.0);
@@ -705,10 +708,17 @@ int upload_weights(mppi_engine* e, const mppi_sdf_weights* w) {
   float bout = 0.0f;
   if (mlp) {
     for (int m = 0; m < H; ++m) {
-      for (int i = 0; i < 3; ++i) w1p[m * 4 + i] = w->W[0][(size_t)m * (3 + D) + i];
-      for (int j = 0; j < D; ++j) w0lat[(size_t)m * D + j] = w->W[0][(size_t)m * (3 + D) + 3 + j];
+      for (int i = 0; i < 3; ++i) w1p[m * 4 + i] = w->W[0][(size_t)m * (NF + D) + i];
+      for (int j = 0; j < D; ++j) w0lat[(size_t)m * D + j] = w->W[0][(size_t)m * (NF + D) + NF + j];
       b0[m] = w->b[0][m];
     }
+    // encoded-point columns as 16x16x4 operand fragments [mb][ks][lane]
+    for (int mb = 0; mb < H / 16 && KQ > 0; ++mb)
+      for (int ks = 0; ks < KQ; ++ks)
+        for (int lane = 0; lane < 64; ++lane) {
+          const int m = 16 * mb + lane % 16, f = 4 * ks + lane / 16;
+          if (f < NF) w1pe[((size_t)mb * KQ + ks) * 64 + lane] = w->W[0][(size_t)m * (NF + D) + f];
+        }
     for (int l = 0; l < L - 1; ++l)
       for (int m = 0; m < H; ++m) hbias[(size_t)l * H + m] = w->b[l + 1][m];
     for (int m = 0; m < H; ++m) wout[m] = w->W[L][m];
@@ -740,7 +750,8 @@ int upload_weights(mppi_engine* e, const mppi_sdf_weights* w) {
   const uint64_t o_ws = align_up(o_lp + hlp.size());
   const uint64_t o_as = align_up(o_ws + 4 * wsc.size());
   const uint64_t o_ai = align_up(o_as + 4 * asc.size());
-  const uint64_t total = align_up(o_ai + 4 * ainv.size());
+  const uint64_t o_pe = align_up(o_ai + 4 * ainv.size());
+  const uint64_t total = align_up(o_pe + 4 * w1pe.size());
   HIPCHK(e, hipMalloc(&e->wmem, total));
   char* b = (char*)e->wmem;
   HIPCHK(e, hipMemcpy(b + o_w1p, w1p.data(), 4 * w1p.size(), hipMemcpyHostToDevice));
@@ -753,6 +764,7 @@ int upload_weights(mppi_engine* e, const mppi_sdf_weights* w) {
   HIPCHK(e, hipMemcpy(b + o_ws, wsc.data(), 4 * wsc.size(), hipMemcpyHostToDevice));
   HIPCHK(e, hipMemcpy(b + o_as, asc.data(), 4 * asc.size(), hipMemcpyHostToDevice));
   HIPCHK(e, hipMemcpy(b + o_ai, ainv.data(), 4 * ainv.size(), hipMemcpyHostToDevice));
+  if (!w1pe.empty()) HIPCHK(e, hipMemcpy(b + o_pe, w1pe.data(), 4 * w1pe.size(), hipMemcpyHostToDevice));
   DeviceWeights& dw = e->dw;
   dw.H = H;
   dw.n_hidden = L;
@@ -768,6 +780,10 @@ int upload_weights(mppi_engine* e, const mppi_sdf_weights* w) {
   dw.w_scale = (const float*)(b + o_ws);
   dw.a_scale = (const float*)(b + o_as);
   dw.a_inv = (const float*)(b + o_ai);
+  dw.pe_freqs = e->cfg.pe_freqs;
+  dw.n_feat = NF;
+  dw.feat_ksteps = KQ;
+  dw.w1pe = w1pe.empty() ? nullptr : (const float*)(b + o_pe);
   return MPPI_OK;
 }
 
@@ -821,6 +837,9 @@ int mppi_create(const mppi_config* cfg, const mppi_sdf_weights* w, mppi_engine**
     if (!isfin(c.u_lo[i]) || !isfin(c.u_hi[i]) || c.u_lo[i] > c.u_hi[i]) return MPPI_EINVAL;
   if (!c.device_pool && c.hbm_budget_bytes == 0) return MPPI_EINVAL;
   if (c.dynamics != MPPI_DYN_CTBR && c.dynamics != MPPI_DYN_ROTOR_RATES) return MPPI_EINVAL;
+  if (c.pe_freqs < 0 || c.pe_freqs > 8) return MPPI_EINVAL;
+  if (c.pe_freqs > 0 && (c.sdf_kind != MPPI_SDF_MLP || (c.path == MPPI_PATH_FUSED && c.hidden > 256)))
+    return MPPI_EINVAL;
   if (c.dynamics == MPPI_DYN_ROTOR_RATES) {
     for (int i = 0; i < 3; ++i)
       if (!(c.inertia[i] > 0.0) || !isfin(c.inertia[i])) return MPPI_EINVAL;

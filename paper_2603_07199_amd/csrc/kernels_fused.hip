@@ -501,16 +501,36 @@ template <int H> struct L1Split {
   __device__ static int first(int wave) { return wave >= kWaves / 2 ? (wave - kWaves / 2) * B : (kWaves / 2) * B + wave * A; }
 };
 
-template <int H, int NB>
+// PE (positional encoding, Section III-B): the point enters as PE(p); the
+// B operand of K-step ks is feature 4 ks + h of the row, computed in place,
+// and the A operands are W1's feature columns (fragments in global memory,
+// read through the caches: 52 KB at most).
+template <int H, int NB, bool PE>
 __device__ __forceinline__ void layer1_products(const float* pts, const float* cf, const float* w1p, int b0, int h,
-                                                int nl, f32x4 (&x)[NB > 0 ? NB : 1]) {
-  const float bk = pts[4 * nl + h];
+                                                int nl, f32x4 (&x)[NB > 0 ? NB : 1], const DeviceWeights& w) {
   const int g = (int)pts[4 * nl + 3];
+  if constexpr (!PE) {
+    const float bk = pts[4 * nl + h];
 #pragma unroll
-  for (int j = 0; j < NB; ++j) {
-    const float4 c4 = *(const float4*)(cf + g * H + 16 * (b0 + j) + 4 * h);
-    x[j] = f32x4{c4.x, c4.y, c4.z, c4.w};
-    x[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(w1p[4 * (16 * (b0 + j) + nl) + h], bk, x[j], 0, 0, 0);
+    for (int j = 0; j < NB; ++j) {
+      const float4 c4 = *(const float4*)(cf + g * H + 16 * (b0 + j) + 4 * h);
+      x[j] = f32x4{c4.x, c4.y, c4.z, c4.w};
+      x[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(w1p[4 * (16 * (b0 + j) + nl) + h], bk, x[j], 0, 0, 0);
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const float4 c4 = *(const float4*)(cf + g * H + 16 * (b0 + j) + 4 * h);
+      x[j] = f32x4{c4.x, c4.y, c4.z, c4.w};
+    }
+    const float px = pts[4 * nl], py = pts[4 * nl + 1], pz = pts[4 * nl + 2];
+    const int KQ = w.feat_ksteps, lane = 16 * h + nl;
+    for (int ks = 0; ks < KQ; ++ks) {
+      const float bk = pe_feature(4 * ks + h, px, py, pz, w.pe_freqs);
+#pragma unroll
+      for (int j = 0; j < NB; ++j)
+        x[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(w.w1pe[((size_t)(b0 + j) * KQ + ks) * 64 + lane], bk, x[j], 0, 0, 0);
+    }
   }
 }
 
@@ -561,7 +581,7 @@ __device__ __forceinline__ void vector_work(const f32x4 (&acc)[MB], const f32x4 
 // the two parts in opposite order (MFIRST: products first), so that one
 // wave's matrix-core work runs beside the other's vector work.  Blocks outside
 // the tile's range run on stale data whose results are never read.
-template <int P, int H, int NHH, int OWN, int PAR, bool MFIRST, int MB>
+template <int P, int H, int NHH, int OWN, int PAR, bool MFIRST, int MB, bool PE>
 __device__ __forceinline__ void pipeline_step(const Views& V, const DeviceWeights& w, int wave, int gw, int h,
                                               int nl, float scale_own, const FragT<P> (&wreg)[MB][H / 32],
                                               f32x4 (&acc)[2][MB], const float* pts_prev, const float* pts_cur,
@@ -582,7 +602,7 @@ __device__ __forceinline__ void pipeline_step(const Views& V, const DeviceWeight
     f32x4 x1[NB > 0 ? NB : 1];
     read_operands<P, H>(in, boff, 0, b0);
     products<P, H, OWN, MB>(in, boff, V.hb, gw, h, wreg, b0, acc[PAR]);
-    layer1_products<H, NB>(pts_prev, V.cf, V.w1p, l1b, h, nl, x1);
+    layer1_products<H, NB, PE>(pts_prev, V.cf, V.w1p, l1b, h, nl, x1, w);
     sched_fence();
     vector_work<P, H, NHH, OWN, MB, NB>(acc[1 - PAR], x1, out, l1out, op, V.hb, V.wo, w, l1b, gw, h, nl, scale_own);
   } else {
@@ -595,14 +615,14 @@ __device__ __forceinline__ void pipeline_step(const Views& V, const DeviceWeight
     vector_work<P, H, NHH, OWN, MB, NB>(acc[1 - PAR], x1c, out, l1out, op, V.hb, V.wo, w, l1b, gw, h, nl, scale_own);
     sched_fence();
     products<P, H, OWN, MB>(in, boff, V.hb, gw, h, wreg, b0, acc[PAR]);
-    layer1_products<H, NB>(pts_cur, V.cf, V.w1p, l1b, h, nl, x1c);
+    layer1_products<H, NB, PE>(pts_cur, V.cf, V.w1p, l1b, h, nl, x1c, w);
   }
 }
 
 // The decoder over one tile's blocks for a wave that owns hidden layer OWN.
 // Activation buffer (l, p) is the input of hidden layer l for blocks of
 // parity p.  Every wave runs the same number of steps and barriers.
-template <int P, int H, int NHH, int OWN, bool MFIRST, int MB>
+template <int P, int H, int NHH, int OWN, bool MFIRST, int MB, bool PE>
 __device__ __forceinline__ void decoder_tile(const Views& V, const SolveDesc& d, const DeviceWeights& w, int wave,
                                              int lane, int gw, int h, int nl, float scale_own,
                                              const FragT<P> (&wreg)[MB][H / 32], int npos, int nblk) {
@@ -640,20 +660,20 @@ __device__ __forceinline__ void decoder_tile(const Views& V, const SolveDesc& d,
     int hv = h, nv = nl;
     asm volatile("" : "+v"(hv), "+v"(nv));
     edges(s, 0);
-    pipeline_step<P, H, NHH, OWN, 0, MFIRST, MB>(V, w, wave, gw, hv, nv, scale_own, wreg, acc,
+    pipeline_step<P, H, NHH, OWN, 0, MFIRST, MB, PE>(V, w, wave, gw, hv, nv, scale_own, wreg, acc,
                                                  slot_pts(slot == 0 ? 2 : slot - 1), slot_pts(slot), x1c);
     __syncthreads();
     slot = slot == 2 ? 0 : slot + 1;
     asm volatile("" : "+v"(hv), "+v"(nv));
     edges(s + 1, 1);
-    pipeline_step<P, H, NHH, OWN, 1, MFIRST, MB>(V, w, wave, gw, hv, nv, scale_own, wreg, acc,
+    pipeline_step<P, H, NHH, OWN, 1, MFIRST, MB, PE>(V, w, wave, gw, hv, nv, scale_own, wreg, acc,
                                                  slot_pts(slot == 0 ? 2 : slot - 1), slot_pts(slot), x1c);
     __syncthreads();
     slot = slot == 2 ? 0 : slot + 1;
   }
 }
 
-template <int P, int H, int NHH>
+template <int P, int H, int NHH, bool PE>
 __global__ __launch_bounds__(kThreads, 1) void k_fused(FusedBatch batch, DeviceWeights w, int Tm, int Gm,
                                                         int max_tiles) {
   using PT = PrecTraits<P>;
@@ -701,12 +721,12 @@ __global__ __launch_bounds__(kThreads, 1) void k_fused(FusedBatch batch, DeviceW
     // epilogue needs the fewest registers beside two accumulator sets)
     const bool mfirst = wave >= kWaves / 2;
     if (NHH == 1) {
-      if (mfirst) decoder_tile<P, H, NHH, 0, true, MB>(V, d, w, wave, lane, gw, h, nl, scale_own, wreg, npos, nblk);
-      else decoder_tile<P, H, NHH, 0, false, MB>(V, d, w, wave, lane, gw, h, nl, scale_own, wreg, npos, nblk);
+      if (mfirst) decoder_tile<P, H, NHH, 0, true, MB, PE>(V, d, w, wave, lane, gw, h, nl, scale_own, wreg, npos, nblk);
+      else decoder_tile<P, H, NHH, 0, false, MB, PE>(V, d, w, wave, lane, gw, h, nl, scale_own, wreg, npos, nblk);
     } else if (own == 0) {
-      decoder_tile<P, H, NHH, 0, false, MB>(V, d, w, wave, lane, gw, h, nl, scale_own, wreg, npos, nblk);
+      decoder_tile<P, H, NHH, 0, false, MB, PE>(V, d, w, wave, lane, gw, h, nl, scale_own, wreg, npos, nblk);
     } else {
-      decoder_tile<P, H, NHH, NHH - 1, true, MB>(V, d, w, wave, lane, gw, h, nl, scale_own, wreg, npos, nblk);
+      decoder_tile<P, H, NHH, NHH - 1, true, MB, PE>(V, d, w, wave, lane, gw, h, nl, scale_own, wreg, npos, nblk);
     }
     tile_epilogue(V, d, k0, Re, tick);
   }
@@ -1202,7 +1222,7 @@ __global__ __launch_bounds__(kWideThreads, 1) void k_wide(FusedBatch batch, Devi
 
 // ------------------------------------------------------------------ host side
 
-template <int P, int H, int NHH>
+template <int P, int H, int NHH, bool PE>
 static hipError_t launch_fused_t(const FusedBatch& b, const DeviceWeights& w, int Tm, int Gm,
                                  int max_tiles, hipStream_t s) {
   const FusedLds L = fused_lds<P, H, NHH>(Tm, Gm, max_tiles);
@@ -1213,7 +1233,7 @@ static hipError_t launch_fused_t(const FusedBatch& b, const DeviceWeights& w, in
     static int max_set = 0;
     std::lock_guard<std::mutex> lock(mu);
     if ((int)L.total > max_set) {
-      hipError_t e = hipFuncSetAttribute((const void*)k_fused<P, H, NHH>,
+      hipError_t e = hipFuncSetAttribute((const void*)k_fused<P, H, NHH, PE>,
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.total);
       if (e != hipSuccess) return e;
       max_set = (int)L.total;
@@ -1224,7 +1244,7 @@ static hipError_t launch_fused_t(const FusedBatch& b, const DeviceWeights& w, in
   if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return e;
   const int grid = std::max(1, std::min(b.n_tiles, ncu));
-  hipLaunchKernelGGL((k_fused<P, H, NHH>), dim3(grid), dim3(kThreads), L.total, s, b, w, Tm,
+  hipLaunchKernelGGL((k_fused<P, H, NHH, PE>), dim3(grid), dim3(kThreads), L.total, s, b, w, Tm,
                      Gm, max_tiles);
   return hipGetLastError();
 }
@@ -1258,10 +1278,12 @@ template <int P>
 static hipError_t launch_fused_p(const FusedBatch& b, const DeviceWeights& w, int Tm, int Gm, int mt,
                                  hipStream_t s) {
   const int nhh = w.n_hidden - 1;
-  if (w.H == 128 && nhh == 1) return launch_fused_t<P, 128, 1>(b, w, Tm, Gm, mt, s);
-  if (w.H == 128 && nhh == 2) return launch_fused_t<P, 128, 2>(b, w, Tm, Gm, mt, s);
-  if (w.H == 256 && nhh == 1) return launch_fused_t<P, 256, 1>(b, w, Tm, Gm, mt, s);
-  if (w.H == 256 && nhh == 2) return launch_fused_t<P, 256, 2>(b, w, Tm, Gm, mt, s);
+  const bool pe = w.feat_ksteps > 0;
+  if (w.H == 128 && nhh == 1) return pe ? launch_fused_t<P, 128, 1, true>(b, w, Tm, Gm, mt, s) : launch_fused_t<P, 128, 1, false>(b, w, Tm, Gm, mt, s);
+  if (w.H == 128 && nhh == 2) return pe ? launch_fused_t<P, 128, 2, true>(b, w, Tm, Gm, mt, s) : launch_fused_t<P, 128, 2, false>(b, w, Tm, Gm, mt, s);
+  if (w.H == 256 && nhh == 1) return pe ? launch_fused_t<P, 256, 1, true>(b, w, Tm, Gm, mt, s) : launch_fused_t<P, 256, 1, false>(b, w, Tm, Gm, mt, s);
+  if (w.H == 256 && nhh == 2) return pe ? launch_fused_t<P, 256, 2, true>(b, w, Tm, Gm, mt, s) : launch_fused_t<P, 256, 2, false>(b, w, Tm, Gm, mt, s);
+  if (pe) return hipErrorInvalidValue;   // the H = 512 decoder has no encoded-point layer 1
   if (w.H == 512 && nhh == 1) return launch_wide_t<P, 512, 1>(b, w, Tm, Gm, mt, s);
   if (w.H == 512 && nhh == 2) return launch_wide_t<P, 512, 2>(b, w, Tm, Gm, mt, s);
   return hipErrorInvalidValue;

@@ -12,6 +12,8 @@
 #include <float.h>
 #include <math.h>
 
+#include <mutex>
+
 #include "device_common.hpp"
 #include "kernels.hpp"
 #include "weights.hpp"
@@ -107,6 +109,7 @@ __global__ __launch_bounds__(256) void k_sdf_f32(const SolveDesc* __restrict__ d
   float* actT = smem;                     // H x ST
   float* pts = actT + H * ST;             // 64 x 3
   float* part = pts + 192;                // 4 x 64
+  float* featT = part + 256;              // positional encoding: 4 feat_ksteps x ST, featT[f][row]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int G = d.G, K = d.K, T = d.T;
   const int P = 64 / G;
@@ -135,18 +138,62 @@ __global__ __launch_bounds__(256) void k_sdf_f32(const SolveDesc* __restrict__ d
   }
   __syncthreads();
 
-  // layer 1 on the vector units: softplus(W1[:, :3] p + c_g)
-  for (int e = tid; e < H * 64; e += 256) {
-    const int n = e & 63, m = e >> 6;
-    const int g = (n / G < P) ? n % G : 0;
-    const float x = fmaf(w.w1p[m * 4 + 0], pts[n * 3 + 0],
-                         fmaf(w.w1p[m * 4 + 1], pts[n * 3 + 1],
-                              fmaf(w.w1p[m * 4 + 2], pts[n * 3 + 2], d.cfold[g * H + m])));
-    actT[m * ST + n] = softplus_accurate(x);
+  const int h = lane >> 4, nl = lane & 15;
+  if (w.feat_ksteps == 0) {
+    // layer 1 on the vector units: softplus(W1[:, :3] p + c_g)
+    for (int e = tid; e < H * 64; e += 256) {
+      const int n = e & 63, m = e >> 6;
+      const int g = (n / G < P) ? n % G : 0;
+      const float x = fmaf(w.w1p[m * 4 + 0], pts[n * 3 + 0],
+                           fmaf(w.w1p[m * 4 + 1], pts[n * 3 + 1],
+                                fmaf(w.w1p[m * 4 + 2], pts[n * 3 + 2], d.cfold[g * H + m])));
+      actT[m * ST + n] = softplus_accurate(x);
+    }
+  } else {
+    // encoded point: the features of the 64 rows, then layer 1 on the matrix
+    // cores, softplus(W1[:, :n_feat] PE(p) + c_g), K-steps of 4 features
+    const int KQ = w.feat_ksteps;
+    for (int e = tid; e < 4 * KQ * 64; e += 256) {
+      const int n = e & 63, f = e >> 6;
+      featT[f * ST + n] = pe_feature(f, pts[n * 3 + 0], pts[n * 3 + 1], pts[n * 3 + 2], w.pe_freqs);
+    }
+    __syncthreads();
+    f32x4 acc[MBW][4];
+#pragma unroll
+    for (int mb = 0; mb < MBW; ++mb) {
+      const int m0 = 16 * (wave * MBW + mb) + 4 * h;
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb) {
+        const int n = 16 * nb + nl;
+        const int g = (n / G < P) ? n % G : 0;
+        const float* c = d.cfold + g * H + m0;
+        acc[mb][nb] = f32x4{c[0], c[1], c[2], c[3]};
+      }
+    }
+    for (int ks = 0; ks < KQ; ++ks) {
+      float bf[4];
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb) bf[nb] = featT[(4 * ks + h) * ST + 16 * nb + nl];
+#pragma unroll
+      for (int mb = 0; mb < MBW; ++mb) {
+        const float a = w.w1pe[((size_t)(wave * MBW + mb) * KQ + ks) * 64 + lane];
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb)
+          acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bf[nb], acc[mb][nb], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int mb = 0; mb < MBW; ++mb) {
+      const int m0 = 16 * (wave * MBW + mb) + 4 * h;
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          actT[(m0 + i) * ST + 16 * nb + nl] = softplus_accurate(acc[mb][nb][i]);
+    }
   }
   __syncthreads();
 
-  const int h = lane >> 4, nl = lane & 15;
   for (int l = 0; l < d.n_hidden - 1; ++l) {
     const float* Wp = w.hidden_f32 + (size_t)l * H * H;
     const float* bias = w.hbias + l * H;
@@ -358,13 +405,18 @@ template <int H>
 static hipError_t launch_sdf_f32_h(const SolveDesc* dd, const DeviceWeights& w, long npos, int G,
                                    hipStream_t s) {
   constexpr int ST = H <= 256 ? 80 : 68;
-  const size_t lds = ((size_t)H * ST + 192 + 256) * sizeof(float);
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_sdf_f32<H>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    attr_set = true;
+  const size_t lds = ((size_t)H * ST + 192 + 256 + (size_t)4 * w.feat_ksteps * ST) * sizeof(float);
+  {
+    // raise the kernel's dynamic LDS limit to the largest size launched so far
+    static std::mutex mu;
+    static size_t max_set = 0;
+    std::lock_guard<std::mutex> lock(mu);
+    if (lds > max_set) {
+      hipError_t e = hipFuncSetAttribute((const void*)k_sdf_f32<H>,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+      max_set = lds;
+    }
   }
   const int P = 64 / G;
   const long blocks = (npos + P - 1) / P;

@@ -25,6 +25,11 @@ struct DeviceWeights {
   const float* w_scale;  // FP8: per hidden layer weight scale
   const float* a_scale;  // FP8: per hidden layer activation scale
   const float* a_inv;    // FP8: 1 / a_scale
+  // positional encoding (pe_freqs > 0): n_feat = 3 + 6 pe_freqs features;
+  // W1's feature columns as 16x16x4 FP32 operand fragments
+  // [H/16][feat_ksteps][64] = W1[16 mb + lane % 16][4 ks + lane / 16] (0 past n_feat)
+  int pe_freqs, n_feat, feat_ksteps;
+  const float* w1pe;
 };
 
 }  // namespace mppi
