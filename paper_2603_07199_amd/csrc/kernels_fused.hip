@@ -101,7 +101,7 @@ __host__ __device__ constexpr size_t act_buf_bytes() {
 }
 
 struct FusedLds {
-  size_t act, w1p, hb, wo, cf, rt, base, los, dp, hinge, pts, opart, jl, wt, fac, misc, xch, total;
+  size_t act, w1p, hb, wo, cf, rt, base, los, dp, hinge, pts, opart, jl, wt, fac, misc, xch, rot, total;
 };
 
 // The activation buffers (input of hidden layer l, block parity p) share
@@ -125,6 +125,7 @@ __host__ __device__ FusedLds fused_lds(int Tm, int Gm, int max_tiles) {
   L.jl = take(sizeof(float) * 2 * kTileR);
   L.wt = take(sizeof(double) * (kTileR + 4));
   L.misc = take(64);
+  L.rot = take(sizeof(float) * 8 * kTileR);
   L.act = take(acts > samp ? acts : samp);
   L.cf = take(sizeof(float) * Gm * H);
   L.rt = take(sizeof(float) * 9 * Gm);
@@ -149,6 +150,7 @@ __host__ __device__ constexpr size_t frag_index(int l, int nb, int ks, int lane)
 // Shared-memory views of one workgroup.
 struct Views {
   char *act, *xch;
+  float* rot;      // rotor-thrust-rate input: thrusts (4) and body rate (3) per rollout
   float *samp, *w1p, *hb, *wo, *cf, *rt, *base, *los, *dp, *hinge, *pts, *opart, *jl;
   double *wt, *fac;
   int* misc;
@@ -175,6 +177,7 @@ __device__ __forceinline__ Views make_views(char* lds, int Tm, int Gm, int max_t
   v.wt = (double*)(lds + L.wt);
   v.fac = (double*)(lds + L.fac);
   v.misc = (int*)(lds + L.misc);
+  v.rot = (float*)(lds + L.rot);
   return v;
 }
 
@@ -312,8 +315,10 @@ __device__ __forceinline__ void tile_noise(const Views& V, const SolveDesc& d, i
 
 // Dynamics of this lane's rollout (lanes < Re): positions into V.dp and the
 // rollout's progress + control + alignment cost into V.jl.  ROTOR: the
-// rotor-thrust-rate input (a separate instance, so that the collective-thrust
-// loop carries no rotor state).
+// rotor-thrust-rate input, whose extra state (thrusts, body rate) lives in
+// LDS (V.rot) between steps: the decoder's weights occupy half the registers
+// for the kernel's life, and rotor state in registers here would push other
+// long-lived values into scratch memory for every tile.
 template <bool ROTOR>
 __device__ __forceinline__ void tile_dynamics(const Views& V, const SolveDesc& d, int tid) {
   const int T = d.T;
@@ -322,8 +327,15 @@ __device__ __forceinline__ void tile_dynamics(const Views& V, const SolveDesc& d
   for (int i = 0; i < 3; ++i) { s.dp[i] = 0.0f; s.dv[i] = 0.0f; }
 #pragma unroll
   for (int i = 0; i < 4; ++i) s.q[i] = d.q0[i];
-  RotorState rs;
-  if constexpr (ROTOR) rotor_init(rs, d);
+  float* rsm = V.rot + 8 * tid;
+  if constexpr (ROTOR) {
+    RotorState rs;
+    rotor_init(rs, d);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) rsm[i] = rs.thr[i];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) rsm[4 + i] = rs.w[i];
+  }
   float* dpk = V.dp + 3 * tid * (T + 1);
   dpk[0] = dpk[1] = dpk[2] = 0.0f;
   float Jc = 0.0f, Jv = 0.0f;
@@ -333,8 +345,17 @@ __device__ __forceinline__ void tile_dynamics(const Views& V, const SolveDesc& d
     Jc = fmaf(u[0], u[0], fmaf(u[1], u[1], fmaf(u[2], u[2], fmaf(u[3], u[3], Jc))));
     if (d.Q_vis != 0.0f) Jv += alignment_term(s.q, V.los[2 * t] - s.dp[0], V.los[2 * t + 1] - s.dp[1]);
     if constexpr (ROTOR) {
+      RotorState rs;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) rs.thr[i] = rsm[i];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) rs.w[i] = rsm[4 + i];
       float uc[4];
       rotor_step(rs, u, d, uc);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) rsm[i] = rs.thr[i];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) rsm[4 + i] = rs.w[i];
       quad_step(s, uc, d.dt, d.inv_mass, d.gravity);
     } else {
       quad_step(s, u, d.dt, d.inv_mass, d.gravity);
@@ -705,9 +726,11 @@ __global__ __launch_bounds__(kThreads, 1) void k_fused(FusedBatch batch, DeviceW
     __syncthreads();
     if (tid == 0) V.misc[0] = (int)atomicAdd(batch.tile_counter, 1u);
     __syncthreads();
-    const int tile = V.misc[0];
+    // uniform across the workgroup: descriptor reads go to scalar registers
+    const int tile = __builtin_amdgcn_readfirstlane(V.misc[0]);
     if (tile >= batch.n_tiles) break;
-    const int2 tl = batch.tiles[tile];
+    const int2 tl0 = batch.tiles[tile];
+    const int2 tl = make_int2(__builtin_amdgcn_readfirstlane(tl0.x), __builtin_amdgcn_readfirstlane(tl0.y));
     const SolveDesc& d = batch.descs[tl.x];
     const int K = d.K, T = d.T, G = d.G;
     const int k0 = tl.y;
@@ -899,6 +922,7 @@ __host__ __device__ FusedLds wide_lds(int Tm, int Gm, int max_tiles) {
   L.jl = take(sizeof(float) * 2 * kTileR);
   L.wt = take(sizeof(double) * (kTileR + 4));
   L.misc = take(64);
+  L.rot = take(sizeof(float) * 8 * kTileR);
   L.pts = take(sizeof(float) * 4 * kTileR * Tm);          // control samples
   L.cf = take(sizeof(float) * Gm * wide_cf_stride<H>());
   L.rt = take(sizeof(float) * 9 * Gm);
@@ -932,6 +956,7 @@ __device__ __forceinline__ Views make_wide_views(char* lds, int Tm, int Gm, int 
   v.wt = (double*)(lds + L.wt);
   v.fac = (double*)(lds + L.fac);
   v.misc = (int*)(lds + L.misc);
+  v.rot = (float*)(lds + L.rot);
   return v;
 }
 
@@ -1203,9 +1228,11 @@ __global__ __launch_bounds__(kWideThreads, 1) void k_wide(FusedBatch batch, Devi
     __syncthreads();
     if (tid == 0) V.misc[0] = (int)atomicAdd(batch.tile_counter, 1u);
     __syncthreads();
-    const int tile = V.misc[0];
+    // uniform across the workgroup: descriptor reads go to scalar registers
+    const int tile = __builtin_amdgcn_readfirstlane(V.misc[0]);
     if (tile >= batch.n_tiles) break;
-    const int2 tl = batch.tiles[tile];
+    const int2 tl0 = batch.tiles[tile];
+    const int2 tl = make_int2(__builtin_amdgcn_readfirstlane(tl0.x), __builtin_amdgcn_readfirstlane(tl0.y));
     const SolveDesc& d = batch.descs[tl.x];
     const int k0 = tl.y;
     const int Re = min(kTileR, d.K - k0);
