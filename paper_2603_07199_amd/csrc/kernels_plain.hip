@@ -100,7 +100,7 @@ __global__ __launch_bounds__(256) void k_rollout(const SolveDesc* __restrict__ d
 // Activations live transposed in LDS (actT[k][row]); hidden-layer weights
 // stream from L2 as pre-packed 16x16x4 operand fragments.  Each wave owns
 // H/64 blocks of 16 output neurons for all 64 rows.
-template <int H>
+template <int H, bool PE>
 __global__ __launch_bounds__(256) void k_sdf_f32(const SolveDesc* __restrict__ dd, DeviceWeights w) {
   const SolveDesc& d = *dd;
   constexpr int ST = H <= 256 ? 80 : 68;  // row stride of actT (floats)
@@ -139,7 +139,7 @@ __global__ __launch_bounds__(256) void k_sdf_f32(const SolveDesc* __restrict__ d
   __syncthreads();
 
   const int h = lane >> 4, nl = lane & 15;
-  if (w.feat_ksteps == 0) {
+  if constexpr (!PE) {
     // layer 1 on the vector units: softplus(W1[:, :3] p + c_g)
     for (int e = tid; e < H * 64; e += 256) {
       const int n = e & 63, m = e >> 6;
@@ -401,7 +401,7 @@ __global__ __launch_bounds__(256) void k_wavg(const SolveDesc* __restrict__ dd) 
 }
 
 // ------------------------------------------------------------------ launchers
-template <int H>
+template <int H, bool PE>
 static hipError_t launch_sdf_f32_h(const SolveDesc* dd, const DeviceWeights& w, long npos, int G,
                                    hipStream_t s) {
   constexpr int ST = H <= 256 ? 80 : 68;
@@ -412,7 +412,7 @@ static hipError_t launch_sdf_f32_h(const SolveDesc* dd, const DeviceWeights& w, 
     static size_t max_set = 0;
     std::lock_guard<std::mutex> lock(mu);
     if (lds > max_set) {
-      hipError_t e = hipFuncSetAttribute((const void*)k_sdf_f32<H>,
+      hipError_t e = hipFuncSetAttribute((const void*)k_sdf_f32<H, PE>,
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       if (e != hipSuccess) return e;
       max_set = lds;
@@ -420,7 +420,7 @@ static hipError_t launch_sdf_f32_h(const SolveDesc* dd, const DeviceWeights& w, 
   }
   const int P = 64 / G;
   const long blocks = (npos + P - 1) / P;
-  hipLaunchKernelGGL(k_sdf_f32<H>, dim3((unsigned)blocks), dim3(256), lds, s, dd, w);
+  hipLaunchKernelGGL((k_sdf_f32<H, PE>), dim3((unsigned)blocks), dim3(256), lds, s, dd, w);
   return hipGetLastError();
 }
 
@@ -441,11 +441,12 @@ hipError_t launch_plain(const SolveDesc* dd, const PlainShape& sh, const DeviceW
     hipLaunchKernelGGL(k_sdf_analytic, dim3((unsigned)((npos + 255) / 256)), dim3(256), 0, s, dd);
     e = hipGetLastError();
   } else {
+    const bool pe = w.feat_ksteps > 0;
     switch (w.H) {
-      case 64: e = launch_sdf_f32_h<64>(dd, w, npos, sh.G, s); break;
-      case 128: e = launch_sdf_f32_h<128>(dd, w, npos, sh.G, s); break;
-      case 256: e = launch_sdf_f32_h<256>(dd, w, npos, sh.G, s); break;
-      case 512: e = launch_sdf_f32_h<512>(dd, w, npos, sh.G, s); break;
+      case 64: e = pe ? launch_sdf_f32_h<64, true>(dd, w, npos, sh.G, s) : launch_sdf_f32_h<64, false>(dd, w, npos, sh.G, s); break;
+      case 128: e = pe ? launch_sdf_f32_h<128, true>(dd, w, npos, sh.G, s) : launch_sdf_f32_h<128, false>(dd, w, npos, sh.G, s); break;
+      case 256: e = pe ? launch_sdf_f32_h<256, true>(dd, w, npos, sh.G, s) : launch_sdf_f32_h<256, false>(dd, w, npos, sh.G, s); break;
+      case 512: e = pe ? launch_sdf_f32_h<512, true>(dd, w, npos, sh.G, s) : launch_sdf_f32_h<512, false>(dd, w, npos, sh.G, s); break;
       default: return hipErrorInvalidValue;
     }
   }
