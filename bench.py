@@ -18,7 +18,7 @@ stream through mppi_submit / mppi_poll, with latency probes of the workload's
 shape) and the FP64 oracle timed on the host cores.
 
     python bench.py [--steps K] [--warmup W] [--path fused|plain]
-                    [--precision bf16x3|bf16x2|bf16|fp8|fp32] [--batch B]
+                    [--precision bf16x3|f16x2|bf16x2|bf16|fp8|fp32] [--batch B]
                     [--workload paper|fleet]
 """
 from __future__ import annotations
@@ -40,7 +40,7 @@ if ROOT not in sys.path:
 import scenarios as sc  # noqa: E402
 
 HBM_PEAK = 8.0e12
-PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "bf16x2": 2500.0, "bf16x3": 2500.0, "fp8": 5000.0}
+PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "bf16x2": 2500.0, "bf16x3": 2500.0, "f16x2": 2500.0, "fp8": 5000.0}
 # the workload (set by --workload): configuration name, shape, decoder
 WORKLOADS = {"paper": ("P2", 1), "fleet": ("S2", 1024)}   # name, default solves per step
 CFG = "P2"
@@ -285,7 +285,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--path", default="fused", choices=["plain", "fused"])
-    ap.add_argument("--precision", default="bf16x3", choices=["fp32", "bf16", "bf16x2", "bf16x3", "fp8"])
+    ap.add_argument("--precision", default="bf16x3", choices=["fp32", "bf16", "bf16x2", "bf16x3", "f16x2", "fp8"])
     ap.add_argument("--batch", type=int, default=0, help="solves per step (default: 1, fleet: 1024)")
     ap.add_argument("--workload", default="paper", choices=sorted(WORKLOADS))
     ap.add_argument("--pe-freqs", type=int, default=0,
@@ -330,7 +330,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp32": "f32", "bf16": "bf16", "bf16x2": "bf16x2", "bf16x3": "bf16x3", "fp8": "fp8"}[args.precision],
+        "dtype": {"fp32": "f32", "bf16": "bf16", "bf16x2": "bf16x2", "bf16x3": "bf16x3", "f16x2": "f16x2",
+                  "fp8": "fp8"}[args.precision],
         "data": "synthetic",
         "config": {"workload": _workload_str(),
                    "path": args.path, "precision": args.precision, "solves_per_step": args.batch,

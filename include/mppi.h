@@ -62,13 +62,16 @@ typedef enum mppi_precision {
   MPPI_PREC_BF16 = 1,   /* BF16 weights and activations, FP32 accumulation */
   MPPI_PREC_BF16X2 = 2, /* BF16 weights, activations split hi + lo in BF16 (two products) */
   MPPI_PREC_FP8 = 3,    /* OCP FP8 E4M3 weights and activations, per-layer scales */
-  MPPI_PREC_BF16X3 = 4  /* BF16 weights, activations split hi + mid + lo in BF16 (three products) */
+  MPPI_PREC_BF16X3 = 4, /* BF16 weights, activations split hi + mid + lo in BF16 (three products) */
+  MPPI_PREC_F16X2 = 5   /* BF16-rounded weights held exactly in FP16 (per-layer power-of-two scale),
+                           activations split hi + lo in FP16 (two products); activations are
+                           capped at 65504 */
 } mppi_precision;
 
 typedef enum mppi_path {
   MPPI_PATH_PLAIN = 0,  /* one solve per launch sequence: rollout, SDF, cost, reduce kernels */
   MPPI_PATH_FUSED = 1   /* rollout + SDF + cost fused per tile, batched across solves;
-                           BF16 / BF16X2 / BF16X3 / FP8 with H in {128, 256, 512} and 1-2 hidden H x H layers */
+                           BF16 / BF16X2 / BF16X3 / F16X2 / FP8 with H in {128, 256, 512} and 1-2 hidden H x H layers */
 } mppi_path;
 
 typedef enum mppi_sdf_kind {

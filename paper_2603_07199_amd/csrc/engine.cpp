@@ -810,7 +810,7 @@ const char* mppi_status_str(int s) {
 int mppi_create(const mppi_config* cfg, const mppi_sdf_weights* w, mppi_engine** out) {
   if (!cfg || !out) return MPPI_EINVAL;
   const mppi_config& c = *cfg;
-  if (c.precision < 0 || c.precision > 4 || c.path < 0 || c.path > 1 || c.sdf_kind < 0 || c.sdf_kind > 1)
+  if (c.precision < 0 || c.precision > 5 || c.path < 0 || c.path > 1 || c.sdf_kind < 0 || c.sdf_kind > 1)
     return MPPI_EINVAL;
   if (c.latent_dim != kLatent) return MPPI_EINVAL;
   if (c.sdf_kind == MPPI_SDF_MLP) {

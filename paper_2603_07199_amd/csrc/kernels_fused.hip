@@ -38,6 +38,9 @@
 //   BF16    weights and activations rounded to bfloat16;
 //   BF16X2  bfloat16 weights, activations split a = hi + lo (two products);
 //   BF16X3  bfloat16 weights, a = hi + mid + lo exactly (three products);
+//   F16X2   the bfloat16-rounded weights held exactly in FP16 under a
+//           per-layer power-of-two scale, activations split a = hi + lo in
+//           FP16 (two FP16 products, |a - hi - lo| <= 2^-22 |a| + 2^-25);
 //   FP8     OCP E4M3 weights with a per-layer scale, E4M3 activations with a
 //           static per-layer scale (saturating).
 #include <hip/hip_runtime.h>
@@ -58,6 +61,8 @@ namespace mppi {
 using f32x4 = __attribute__((ext_vector_type(4))) float;
 using bf16x8 = __attribute__((ext_vector_type(8))) __bf16;
 using bf16x2v = __attribute__((ext_vector_type(2))) __bf16;
+using f16x8 = __attribute__((ext_vector_type(8))) _Float16;
+using f16x2v = __attribute__((ext_vector_type(2))) _Float16;
 
 constexpr int kWaves = 8;            // waves per workgroup
 constexpr int kThreads = 64 * kWaves;
@@ -65,13 +70,24 @@ constexpr int kTileR = 16;           // rollouts per tile
 constexpr int kRows = 16;            // query rows per pipeline block
 __host__ __device__ constexpr int kPartStride(int T) { return 4 + 4 * T; }
 
-enum { P_BF16 = 1, P_BF16X2 = 2, P_FP8 = 3, P_BF16X3 = 4 };
+enum { P_BF16 = 1, P_BF16X2 = 2, P_FP8 = 3, P_BF16X3 = 4, P_F16X2 = 5 };
 
+// splits: activation terms (one product each); fp8 / f16: operand type;
+// scaled: the weights carry a per-layer scale.  FP8 starts the accumulators
+// at zero and its epilogue forms scale * acc + bias; F16X2 (power-of-two
+// scale 2^-s) starts them at 2^s bias, kept pre-scaled in LDS, and its
+// epilogue forms scale * acc, both exact scalings; the bfloat16 kinds start
+// them at the bias.
 template <int P> struct PrecTraits;
-template <> struct PrecTraits<P_BF16> { static constexpr int splits = 1; static constexpr bool fp8 = false; };
-template <> struct PrecTraits<P_BF16X2> { static constexpr int splits = 2; static constexpr bool fp8 = false; };
-template <> struct PrecTraits<P_BF16X3> { static constexpr int splits = 3; static constexpr bool fp8 = false; };
-template <> struct PrecTraits<P_FP8> { static constexpr int splits = 1; static constexpr bool fp8 = true; };
+template <int NS, bool F8, bool F16> struct PrecBase {
+  static constexpr int splits = NS;
+  static constexpr bool fp8 = F8, f16 = F16, scaled = F8 || F16;
+};
+template <> struct PrecTraits<P_BF16> : PrecBase<1, false, false> {};
+template <> struct PrecTraits<P_BF16X2> : PrecBase<2, false, false> {};
+template <> struct PrecTraits<P_BF16X3> : PrecBase<3, false, false> {};
+template <> struct PrecTraits<P_FP8> : PrecBase<1, true, false> {};
+template <> struct PrecTraits<P_F16X2> : PrecBase<2, false, true> {};
 
 // max(x, 0) as one integer max on the bit pattern (negative floats, -0
 // included, are negative integers); a float max would first quiet a
@@ -189,6 +205,33 @@ __device__ __forceinline__ uint32_t pack_bf16(float a, float b) {
 __device__ __forceinline__ float bf16_lo(uint32_t w) { return __uint_as_float(w << 16); }
 __device__ __forceinline__ float bf16_hi(uint32_t w) { return __uint_as_float(w & 0xFFFF0000u); }
 
+// The same for IEEE half precision.  Activations (softplus outputs, >= 0)
+// are first capped at the largest finite half, 65504, as an integer min on
+// the bit pattern, so the split never produces an infinity.
+__device__ __forceinline__ uint32_t pack_f16(float a, float b) {
+  const f16x2v t = {(_Float16)a, (_Float16)b};
+  return __builtin_bit_cast(uint32_t, t);
+}
+__device__ __forceinline__ float f16_lo(uint32_t w) { return (float)__builtin_bit_cast(f16x2v, w)[0]; }
+__device__ __forceinline__ float f16_hi(uint32_t w) { return (float)__builtin_bit_cast(f16x2v, w)[1]; }
+__device__ __forceinline__ float cap_f16(float x) {
+  const int i = __float_as_int(x);
+  return __int_as_float(i < 0x477FE000 ? i : 0x477FE000);
+}
+
+// Two-term half split of 4 non-negative activations: hi = RNE half of the
+// capped value, lo = RNE half of the exact remainder.  Returns hi in h[0..1],
+// lo in l[0..1] (two halves per word).
+__device__ __forceinline__ void split_f16(const float* v, uint32_t (&h)[2], uint32_t (&l)[2]) {
+  float a[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) a[i] = cap_f16(v[i]);
+  h[0] = pack_f16(a[0], a[1]);
+  h[1] = pack_f16(a[2], a[3]);
+  l[0] = pack_f16(a[0] - f16_lo(h[0]), a[1] - f16_hi(h[0]));
+  l[1] = pack_f16(a[2] - f16_lo(h[1]), a[3] - f16_hi(h[1]));
+}
+
 // Byte offset of (row n, neuron / K index m) inside one split term of an
 // activation buffer, and the byte size of one split term.
 template <int P, int H>
@@ -216,6 +259,11 @@ __device__ __forceinline__ void put_act(char* buf, uint32_t off, const float v[4
     uint32_t word = __builtin_amdgcn_cvt_pk_fp8_f32(q[0], q[1], 0, false);
     word = __builtin_amdgcn_cvt_pk_fp8_f32(q[2], q[3], word, true);
     *(uint32_t*)(buf + off) = word;
+  } else if constexpr (PT::f16) {
+    uint32_t h[2], l[2];
+    split_f16(v, h, l);
+    *(uint2*)(buf + off) = make_uint2(h[0], h[1]);
+    *(uint2*)(buf + off + act_term_bytes<P, H>()) = make_uint2(l[0], l[1]);
   } else {
     constexpr int NS = PT::splits;
     float r0 = v[0], r1 = v[1], r2 = v[2], r3 = v[3];
@@ -234,7 +282,16 @@ __device__ __forceinline__ void put_act(char* buf, uint32_t off, const float v[4
 }
 
 template <int P>
-using FragT = typename std::conditional<PrecTraits<P>::fp8, long, bf16x8>::type;
+using FragT = typename std::conditional<PrecTraits<P>::fp8, long,
+                                        typename std::conditional<PrecTraits<P>::f16, f16x8, bf16x8>::type>::type;
+
+// One 16x16x32 matrix-core product of the precision's operand type.
+template <int P>
+__device__ __forceinline__ f32x4 mfma_lp(const FragT<P>& a, const FragT<P>& b, const f32x4& c) {
+  if constexpr (PrecTraits<P>::fp8) return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, b, c, 0, 0, 0);
+  else if constexpr (PrecTraits<P>::f16) return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+  else return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
 
 // Per-tile constants of the decoder's edge work (points and output
 // reduction), read once per tile: the loop's scheduling fences would
@@ -460,7 +517,22 @@ __device__ __forceinline__ void sched_fence() {
 }
 
 template <int P>
-using BFragT = typename std::conditional<PrecTraits<P>::fp8, long, bf16x8>::type;
+using BFragT = FragT<P>;
+
+// Pre-activation of one hidden neuron from its accumulator (see PrecBase).
+template <int P>
+__device__ __forceinline__ float pre_act(float acc, float scale, float bias) {
+  if constexpr (PrecTraits<P>::fp8) return fmaf(acc, scale, bias);
+  else if constexpr (PrecTraits<P>::f16) return acc * scale;
+  else return acc;
+}
+
+// Hidden-layer bias as the accumulators' start value (F16X2: times 2^s).
+template <int P>
+__device__ __forceinline__ float bias_start(float b, float scale) {
+  if constexpr (PrecTraits<P>::f16) return b / scale;
+  else return b;
+}
 
 // B operands (16 rows x 32 K of every split term) of K-step ks from `in`;
 // `off` is the lane's byte offset act_off(row, 8 (lane / 16)).
@@ -471,7 +543,7 @@ __device__ __forceinline__ void read_operands(const char* in, uint32_t off, int 
 #pragma unroll
   for (int sp = 0; sp < NS; ++sp) {
     if constexpr (PrecTraits<P>::fp8) b[sp] = *(const long*)(in + off + 32 * ks);
-    else b[sp] = __builtin_bit_cast(bf16x8, *(const uint4*)(in + off + sp * act_term_bytes<P, H>() + 64 * ks));
+    else b[sp] = __builtin_bit_cast(BFragT<P>, *(const uint4*)(in + off + sp * act_term_bytes<P, H>() + 64 * ks));
   }
 }
 
@@ -498,8 +570,7 @@ __device__ __forceinline__ void products(const char* in, uint32_t boff, const fl
     for (int sp = 0; sp < NS; ++sp)
 #pragma unroll
       for (int mb = 0; mb < MB; ++mb) {
-        if constexpr (PT::fp8) acc[mb] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(wreg[mb][ks], b0[sp], acc[mb], 0, 0, 0);
-        else acc[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wreg[mb][ks], b0[sp], acc[mb], 0, 0, 0);
+        acc[mb] = mfma_lp<P>(wreg[mb][ks], b0[sp], acc[mb]);
       }
 #pragma unroll
     for (int sp = 0; sp < NS; ++sp) b0[sp] = bn[sp];
@@ -572,7 +643,7 @@ __device__ __forceinline__ void vector_work(const f32x4 (&acc)[MB], const f32x4 
     float v[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
-      v[i] = softplus_fast(PT::fp8 ? fmaf(acc[mb][i], scale_own, hb[OWN * H + e0 + 16 * mb + i]) : acc[mb][i]);
+      v[i] = softplus_fast(pre_act<P>(acc[mb][i], scale_own, PT::fp8 ? hb[OWN * H + e0 + 16 * mb + i] : 0.0f));
     if constexpr (OWN + 1 < NHH) {
       put_act<P, H>(out, eoff + act_off<P, H>(0, 16 * mb), v, PT::fp8 ? w.a_inv[OWN + 1] : 1.0f);
     } else {
@@ -715,11 +786,11 @@ __global__ __launch_bounds__(kThreads, 1) void k_fused(FusedBatch batch, DeviceW
     for (int ks = 0; ks < KS; ++ks) {
       const size_t fi = frag_index<H>(own, gw * MB + mb, ks, lane);
       if constexpr (PT::fp8) wreg[mb][ks] = ((const long*)w.hidden_lp)[fi];
-      else wreg[mb][ks] = __builtin_bit_cast(bf16x8, ((const uint4*)w.hidden_lp)[fi]);
+      else wreg[mb][ks] = __builtin_bit_cast(FragT<P>, ((const uint4*)w.hidden_lp)[fi]);
     }
-  const float scale_own = PT::fp8 ? w.w_scale[own] * w.a_scale[own] : 1.0f;
+  const float scale_own = PT::scaled ? w.w_scale[own] * w.a_scale[own] : 1.0f;
   for (int i = tid; i < 4 * H; i += kThreads) V.w1p[i] = w.w1p[i];
-  for (int i = tid; i < NHH * H; i += kThreads) V.hb[i] = w.hbias[i];
+  for (int i = tid; i < NHH * H; i += kThreads) V.hb[i] = bias_start<P>(w.hbias[i], PT::scaled ? w.w_scale[i / H] : 1.0f);
   for (int i = tid; i < H; i += kThreads) V.wo[i] = w.wout[i];
 
   while (true) {
@@ -997,6 +1068,11 @@ __device__ __forceinline__ void wide_put_half(char* x, int lane, int par, float 
     uint32_t w = __builtin_amdgcn_cvt_pk_fp8_f32(q[0], q[1], 0u, false);
     w = __builtin_amdgcn_cvt_pk_fp8_f32(q[2], q[3], w, true);
     *(uint32_t*)(x + lane * 8 + 4 * par) = w;
+  } else if constexpr (PT::f16) {
+    uint32_t h[2], l[2];
+    split_f16(v, h, l);
+    *(uint2*)(x + lane * 16 + 8 * par) = make_uint2(h[0], h[1]);
+    *(uint2*)(x + wide_xterm_bytes<P>() + lane * 16 + 8 * par) = make_uint2(l[0], l[1]);
   } else {
 #pragma unroll
     for (int sp = 0; sp < PT::splits; ++sp) {
@@ -1031,8 +1107,9 @@ __device__ __forceinline__ void wide_l1_half(const Views& V, const float (&pt)[4
 }
 
 // Half operand of K-step ks of the next hidden layer from this wave's
-// accumulator block m = ks (neurons 32 ks + 16 par + 4 hq + i); FP8: scaled,
-// plus the bias (the bfloat16 kinds start the accumulators at the bias).
+// accumulator block m = ks (neurons 32 ks + 16 par + 4 hq + i); FP8 scales
+// and adds the bias here, F16X2 scales (its accumulators start at the scaled
+// bias), the bfloat16 kinds start the accumulators at the bias.
 template <int P>
 __device__ __forceinline__ void wide_epi_half(const f32x4& acc, const float* hb, float scale, int ks, int hq, int par,
                                               int lane, float inv, char* x) {
@@ -1041,7 +1118,7 @@ __device__ __forceinline__ void wide_epi_half(const f32x4& acc, const float* hb,
   if constexpr (PrecTraits<P>::fp8) bb = *(const float4*)(hb + 32 * ks + 16 * par + 4 * hq);
   const float bv[4] = {bb.x, bb.y, bb.z, bb.w};
 #pragma unroll
-  for (int i = 0; i < 4; ++i) v[i] = softplus_fast(PrecTraits<P>::fp8 ? fmaf(acc[i], scale, bv[i]) : acc[i]);
+  for (int i = 0; i < 4; ++i) v[i] = softplus_fast(pre_act<P>(acc[i], scale, bv[i]));
   wide_put_half<P>(x, lane, par, v, inv);
 }
 
@@ -1061,7 +1138,7 @@ __device__ __forceinline__ void wide_step(const char* slice, const char* xin, in
 #pragma unroll
   for (int sp = 0; sp < NS; ++sp) {
     if constexpr (PT::fp8) bf[sp] = *(const long*)(xin + lane * 8);
-    else bf[sp] = __builtin_bit_cast(bf16x8, *(const uint4*)(xin + sp * wide_xterm_bytes<P>() + lane * 16));
+    else bf[sp] = __builtin_bit_cast(BFragT<P>, *(const uint4*)(xin + sp * wide_xterm_bytes<P>() + lane * 16));
   }
   if constexpr (VFIRST) {
     prep();
@@ -1084,8 +1161,7 @@ __device__ __forceinline__ void wide_step(const char* slice, const char* xin, in
 #pragma unroll
       for (int i = 0; i < GR; ++i) {
         f32x4& c = acc[g * GR + i];
-        if constexpr (PT::fp8) c = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a[g & 1][i], bf[sp], c, 0, 0, 0);
-        else c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[g & 1][i], bf[sp], c, 0, 0, 0);
+        c = mfma_lp<P>(a[g & 1][i], bf[sp], c);
       }
     sched_fence();
   }
@@ -1116,8 +1192,7 @@ __device__ __forceinline__ void wide_output_part(const Views& V, const f32x4 (&a
     if constexpr (PrecTraits<P>::fp8) bb = *(const float4*)(hb + n0);
     const float ow[4] = {o4.x, o4.y, o4.z, o4.w}, bv[4] = {bb.x, bb.y, bb.z, bb.w};
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-      op = fmaf(ow[i], softplus_fast(PrecTraits<P>::fp8 ? fmaf(acc[m][i], scale, bv[i]) : acc[m][i]), op);
+    for (int i = 0; i < 4; ++i) op = fmaf(ow[i], softplus_fast(pre_act<P>(acc[m][i], scale, bv[i])), op);
   }
   op += __shfl_xor(op, 16, 64);
   op += __shfl_xor(op, 32, 64);
@@ -1156,8 +1231,8 @@ __device__ __forceinline__ void wide_tile(const Views& V, const DeviceWeights& w
   float* opp = V.opart + rb * 2 * kRows;
   const float inv1 = PT::fp8 ? w.a_inv[0] : 1.0f;
   const float invB = (PT::fp8 && NHH == 2) ? w.a_inv[NHH - 1] : 1.0f;
-  const float sA = PT::fp8 ? w.w_scale[0] * w.a_scale[0] : 1.0f;
-  const float sB = PT::fp8 ? w.w_scale[NHH - 1] * w.a_scale[NHH - 1] : 1.0f;
+  const float sA = PT::scaled ? w.w_scale[0] * w.a_scale[0] : 1.0f;
+  const float sB = PT::scaled ? w.w_scale[NHH - 1] * w.a_scale[NHH - 1] : 1.0f;
   const int nblk = (npos + kRows / d.G - 1) / (kRows / d.G);
   const int npass = (nblk + kWidePairs - 1) / kWidePairs;
   const EdgeConsts ec = edge_consts(d, nl, npos, w.bout);
@@ -1222,7 +1297,7 @@ __global__ __launch_bounds__(kWideThreads, 1) void k_wide(FusedBatch batch, Devi
   const Views V = make_wide_views<P, H, NHH>(lds, Tm, Gm, max_tiles);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   for (int i = tid; i < 4 * H; i += kWideThreads) V.w1p[i] = w.w1p[i];
-  for (int i = tid; i < NHH * H; i += kWideThreads) V.hb[i] = w.hbias[i];
+  for (int i = tid; i < NHH * H; i += kWideThreads) V.hb[i] = bias_start<P>(w.hbias[i], PrecTraits<P>::scaled ? w.w_scale[i / H] : 1.0f);
   for (int i = tid; i < H; i += kWideThreads) V.wo[i] = w.wout[i];
   while (true) {
     __syncthreads();
@@ -1327,6 +1402,7 @@ hipError_t launch_fused(const FusedBatch& b, int n_solves, const DeviceWeights& 
     case P_BF16X2: e = launch_fused_p<P_BF16X2>(b, w, max_T, max_G, max_tiles, s); break;
     case P_BF16X3: e = launch_fused_p<P_BF16X3>(b, w, max_T, max_G, max_tiles, s); break;
     case P_FP8: e = launch_fused_p<P_FP8>(b, w, max_T, max_G, max_tiles, s); break;
+    case P_F16X2: e = launch_fused_p<P_F16X2>(b, w, max_T, max_G, max_tiles, s); break;
     default: return hipErrorInvalidValue;
   }
   if (e != hipSuccess) return e;
@@ -1339,7 +1415,9 @@ hipError_t launch_fused(const FusedBatch& b, int n_solves, const DeviceWeights& 
 int fused_tile_rollouts(int, int, int) { return kTileR; }
 
 bool fused_supported(int precision, int H, int n_hidden) {
-  if (!(precision == P_BF16 || precision == P_BF16X2 || precision == P_BF16X3 || precision == P_FP8)) return false;
+  if (!(precision == P_BF16 || precision == P_BF16X2 || precision == P_BF16X3 || precision == P_FP8 ||
+        precision == P_F16X2))
+    return false;
   return (H == 128 || H == 256 || H == 512) && (n_hidden == 2 || n_hidden == 3);
 }
 
@@ -1357,6 +1435,7 @@ size_t fused_lds_bytes(int precision, int H, int n_hidden, int Tm, int Gm, int m
     case P_BF16X2: return pick(std::integral_constant<int, P_BF16X2>{});
     case P_BF16X3: return pick(std::integral_constant<int, P_BF16X3>{});
     case P_FP8: return pick(std::integral_constant<int, P_FP8>{});
+    case P_F16X2: return pick(std::integral_constant<int, P_F16X2>{});
   }
   return 0;
 }
@@ -1368,6 +1447,21 @@ static uint16_t host_bf16_rne(float f) {
   memcpy(&u, &f, 4);
   u += 0x7FFFu + ((u >> 16) & 1u);
   return (uint16_t)(u >> 16);
+}
+
+// IEEE half, round to nearest even (subnormals included; beyond 65504 rounds
+// to the largest finite value, which the callers' scaling never reaches).
+static uint16_t host_f16_rne(float x) {
+  const uint16_t sign = std::signbit(x) ? 0x8000 : 0x0000;
+  const double a = fabs((double)x);
+  if (a < 0x1p-14) return sign | (uint16_t)nearbyint(a * 0x1p24);   // 1024 encodes 2^-14 itself
+  int e;
+  double m = frexp(a, &e);                // a = m 2^e, m in [0.5, 1)
+  double q = nearbyint(m * 2048.0);       // 11 significant bits
+  if (q == 2048.0) { q = 1024.0; ++e; }
+  const int E = e - 1 + 15;
+  if (E >= 31) return sign | 0x7BFF;
+  return sign | (uint16_t)((E << 10) | ((int)q - 1024));
 }
 
 // OCP E4M3 (bias 7, max 448, no infinities), round to nearest even, saturating.
@@ -1397,7 +1491,7 @@ int pack_lowp_weights(int precision, int H, int n_hidden, const mppi_sdf_weights
   if (!fused_supported(precision, H, n_hidden)) return MPPI_EINVAL;
   const int nhh = n_hidden - 1;
   const int NB = H / 16, KS = H / 32;
-  const bool fp8 = precision == P_FP8;
+  const bool fp8 = precision == P_FP8, f16 = precision == P_F16X2;
   const size_t esz = fp8 ? 8 : 16;
   blob.assign((size_t)nhh * NB * KS * 64 * esz, 0);
   w_scale.assign(nhh, 1.0f);
@@ -1415,6 +1509,22 @@ int pack_lowp_weights(int precision, int H, int n_hidden, const mppi_sdf_weights
       if (!(as > 0.0f) || !std::isfinite(as)) return MPPI_EINVAL;
       a_scale[l] = as;
       a_inv[l] = 1.0f / as;
+    } else if (f16) {
+      // power-of-two scale 2^-s with the largest bfloat16 weight times 2^s in
+      // [2^14, 2^15): every bfloat16 weight within 2^-29 of the largest then
+      // has an exact normal half image (8 significant bits of 11)
+      float amax = 0.0f;
+      for (size_t i = 0; i < (size_t)H * H; ++i) {
+        const uint32_t hb = (uint32_t)host_bf16_rne(W[i]) << 16;
+        float b;
+        memcpy(&b, &hb, 4);
+        amax = std::max(amax, fabsf(b));
+      }
+      if (!std::isfinite(amax)) return MPPI_EINVAL;
+      int e = 0;
+      if (amax > 0.0f) frexpf(amax, &e);    // amax in [2^(e-1), 2^e)
+      scale = amax > 0.0f ? ldexpf(1.0f, e - 15) : 1.0f;
+      w_scale[l] = scale;
     }
     // H <= 256: fragment (l, nb, ks, lane) at (((l NB + nb) KS + ks) 64 + lane),
     // as frag_index<H> lays it out, operand slot j = input 32 ks + 8 (lane / 16) + j.
@@ -1432,6 +1542,12 @@ int pack_lowp_weights(int precision, int H, int n_hidden, const mppi_sdf_weights
             const float v = W[(size_t)m * H + k];
             if (fp8) {
               blob[fi * 8 + j] = host_e4m3(v / scale);
+            } else if (f16) {
+              const uint32_t hb = (uint32_t)host_bf16_rne(v) << 16;
+              float b;
+              memcpy(&b, &hb, 4);
+              const uint16_t h = host_f16_rne(b / scale);   // exact power-of-two scaling
+              memcpy(&blob[fi * 16 + 2 * j], &h, 2);
             } else {
               const uint16_t b = host_bf16_rne(v);
               memcpy(&blob[fi * 16 + 2 * j], &b, 2);

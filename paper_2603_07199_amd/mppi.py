@@ -23,7 +23,7 @@ MPPI_OK, MPPI_PENDING = 0, 1
 MPPI_EINVAL, MPPI_ENOMEM, MPPI_EAGAIN = -1, -2, -3
 MPPI_ENOTFOUND, MPPI_ENUMERIC, MPPI_EDEVICE = -4, -5, -6
 
-PREC = {"fp32": 0, "bf16": 1, "bf16x2": 2, "fp8": 3, "bf16x3": 4}
+PREC = {"fp32": 0, "bf16": 1, "bf16x2": 2, "fp8": 3, "bf16x3": 4, "f16x2": 5}
 PATH = {"plain": 0, "fused": 1}
 SDF = {"mlp": 0, "analytic": 1}
 CFG_TIMING = 1
