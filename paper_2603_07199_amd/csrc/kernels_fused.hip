@@ -104,6 +104,25 @@ __device__ __forceinline__ float softplus_fast(float x) {
   return fmaf(__builtin_amdgcn_logf(1.0f + e), 0.6931471805599453f, relu_bits(x));
 }
 
+// softplus whose result stays within the finite half range: max(x, 0) is
+// taken as min(max(x, 0), 65503) in one integer med3 on the bit pattern; the
+// logarithmic term adds less than 2^-1000 there, so the result is at most
+// 65503.  Differs from softplus only for x > 65503.
+__device__ __forceinline__ float softplus_capped(float x) {
+  const float e = __builtin_amdgcn_exp2f(-fabsf(x) * 1.4426950408889634f);
+  const int i = __float_as_int(x);
+  const int r = i > 0 ? (i < 0x477FDF00 ? i : 0x477FDF00) : 0;   // 65503.0f
+  return fmaf(__builtin_amdgcn_logf(1.0f + e), 0.6931471805599453f, __int_as_float(r));
+}
+
+// Activation that becomes the next layer's operand: F16X2 needs it within
+// the half range.
+template <int P>
+__device__ __forceinline__ float softplus_act(float x) {
+  if constexpr (PrecTraits<P>::f16) return softplus_capped(x);
+  else return softplus_fast(x);
+}
+
 // LDS activation row stride in elements (bf16) / bytes (fp8): the pad keeps
 // 16-byte operand reads of 16 consecutive rows on distinct banks.
 template <int H> __host__ __device__ constexpr int act_stride_bf16() { return H + 8; }
@@ -205,31 +224,41 @@ __device__ __forceinline__ uint32_t pack_bf16(float a, float b) {
 __device__ __forceinline__ float bf16_lo(uint32_t w) { return __uint_as_float(w << 16); }
 __device__ __forceinline__ float bf16_hi(uint32_t w) { return __uint_as_float(w & 0xFFFF0000u); }
 
-// The same for IEEE half precision.  Activations (softplus outputs, >= 0)
-// are first capped at the largest finite half, 65504, as an integer min on
-// the bit pattern, so the split never produces an infinity.
+// The same for IEEE half precision (round to nearest even).
 __device__ __forceinline__ uint32_t pack_f16(float a, float b) {
   const f16x2v t = {(_Float16)a, (_Float16)b};
   return __builtin_bit_cast(uint32_t, t);
 }
-__device__ __forceinline__ float f16_lo(uint32_t w) { return (float)__builtin_bit_cast(f16x2v, w)[0]; }
-__device__ __forceinline__ float f16_hi(uint32_t w) { return (float)__builtin_bit_cast(f16x2v, w)[1]; }
-__device__ __forceinline__ float cap_f16(float x) {
-  const int i = __float_as_int(x);
-  return __int_as_float(i < 0x477FE000 ? i : 0x477FE000);
+
+// a - (half h of word w), in one mixed-precision FMA that reads the half
+// straight from the packed word: exact, since the half is a's own rounding.
+__device__ __forceinline__ float rem_f16_lo(uint32_t w, float a) {
+  float r;
+  asm("v_fma_mix_f32 %0, -%1, 1.0, %2 op_sel_hi:[1,0,0]" : "=v"(r) : "v"(w), "v"(a));
+  return r;
+}
+__device__ __forceinline__ float rem_f16_hi(uint32_t w, float a) {
+  float r;
+  asm("v_fma_mix_f32 %0, -%1, 1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "=v"(r) : "v"(w), "v"(a));
+  return r;
 }
 
-// Two-term half split of 4 non-negative activations: hi = RNE half of the
-// capped value, lo = RNE half of the exact remainder.  Returns hi in h[0..1],
-// lo in l[0..1] (two halves per word).
+// Two-term half split of 4 activations in [0, 65503]: hi = RNE half of the
+// value, lo = RNE half of the exact remainder; hi in h[0..1], lo in l[0..1]
+// (two halves per word).  The values are kept opaque before the packing so
+// that the compiler forms hi from the float32 activation (not from a fused
+// re-evaluation of the softplus, one more instruction per pair).
 __device__ __forceinline__ void split_f16(const float* v, uint32_t (&h)[2], uint32_t (&l)[2]) {
   float a[4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) a[i] = cap_f16(v[i]);
+  for (int i = 0; i < 4; ++i) {
+    a[i] = v[i];
+    asm("" : "+v"(a[i]));
+  }
   h[0] = pack_f16(a[0], a[1]);
   h[1] = pack_f16(a[2], a[3]);
-  l[0] = pack_f16(a[0] - f16_lo(h[0]), a[1] - f16_hi(h[0]));
-  l[1] = pack_f16(a[2] - f16_lo(h[1]), a[3] - f16_hi(h[1]));
+  l[0] = pack_f16(rem_f16_lo(h[0], a[0]), rem_f16_hi(h[0], a[1]));
+  l[1] = pack_f16(rem_f16_lo(h[1], a[2]), rem_f16_hi(h[1], a[3]));
 }
 
 // Byte offset of (row n, neuron / K index m) inside one split term of an
@@ -642,8 +671,10 @@ __device__ __forceinline__ void vector_work(const f32x4 (&acc)[MB], const f32x4 
   for (int mb = 0; mb < MB; ++mb) {
     float v[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-      v[i] = softplus_fast(pre_act<P>(acc[mb][i], scale_own, PT::fp8 ? hb[OWN * H + e0 + 16 * mb + i] : 0.0f));
+    for (int i = 0; i < 4; ++i) {
+      const float x = pre_act<P>(acc[mb][i], scale_own, PT::fp8 ? hb[OWN * H + e0 + 16 * mb + i] : 0.0f);
+      v[i] = OWN + 1 < NHH ? softplus_act<P>(x) : softplus_fast(x);
+    }
     if constexpr (OWN + 1 < NHH) {
       put_act<P, H>(out, eoff + act_off<P, H>(0, 16 * mb), v, PT::fp8 ? w.a_inv[OWN + 1] : 1.0f);
     } else {
@@ -658,7 +689,7 @@ __device__ __forceinline__ void vector_work(const f32x4 (&acc)[MB], const f32x4 
   for (int j = 0; j < NB; ++j) {
     float v[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) v[i] = softplus_fast(x[j][i]);
+    for (int i = 0; i < 4; ++i) v[i] = softplus_act<P>(x[j][i]);
     put_act<P, H>(l1out, loff + act_off<P, H>(0, 16 * j), v, PT::fp8 ? w.a_inv[0] : 1.0f);
     if (j & 1) sched_fence();
   }
@@ -1101,7 +1132,7 @@ __device__ __forceinline__ void wide_l1_half(const Views& V, const float (&pt)[4
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const float4 w = *(const float4*)(V.w1p + 4 * (n0 + i));
-    v[i] = softplus_fast(fmaf(w.x, pt[0], fmaf(w.y, pt[1], fmaf(w.z, pt[2], cc[i]))));
+    v[i] = softplus_act<P>(fmaf(w.x, pt[0], fmaf(w.y, pt[1], fmaf(w.z, pt[2], cc[i]))));
   }
   wide_put_half<P>(x, lane, par, v, inv);
 }
@@ -1118,7 +1149,7 @@ __device__ __forceinline__ void wide_epi_half(const f32x4& acc, const float* hb,
   if constexpr (PrecTraits<P>::fp8) bb = *(const float4*)(hb + 32 * ks + 16 * par + 4 * hq);
   const float bv[4] = {bb.x, bb.y, bb.z, bb.w};
 #pragma unroll
-  for (int i = 0; i < 4; ++i) v[i] = softplus_fast(pre_act<P>(acc[i], scale, bv[i]));
+  for (int i = 0; i < 4; ++i) v[i] = softplus_act<P>(pre_act<P>(acc[i], scale, bv[i]));
   wide_put_half<P>(x, lane, par, v, inv);
 }
 
