@@ -13,7 +13,8 @@ RNG tick advance on the device from step to step.
 Prints one JSON line: rollout-steps/s (value), per-step latency p50/p99, the
 roofline of the dominant kernel (HIP-event durations recorded by the library
 on its own stream), the FP32 plain one-solve-per-launch path on the same
-workload for comparison, a served leg (uneven requests arriving as a Poisson
+workload for comparison, the F16X2 kind of the fused path beside the BF16X3
+default, a served leg (uneven requests arriving as a Poisson
 stream through mppi_submit / mppi_poll, with latency probes of the workload's
 shape) and the FP64 oracle timed on the host cores.
 
@@ -355,6 +356,14 @@ def main():
         out["fp32_plain"] = {"rollout_steps_per_s": ref["rollout_steps_per_s"],
                              "ms_per_step": ref["ms_per_step"],
                              "speedup": main_leg["rollout_steps_per_s"] / ref["rollout_steps_per_s"]}
+    if not args.no_compare and args.path == "fused" and args.precision == "bf16x3":
+        # the same bfloat16-weight network to float32 accuracy with two FP16
+        # products per K-step instead of three bfloat16 ones
+        alt = run_leg(M, "fused", "f16x2", args.batch, max(3, args.steps // 2), 1)
+        out["f16x2"] = {"rollout_steps_per_s": alt["rollout_steps_per_s"], "ms_per_step": alt["ms_per_step"],
+                        "kernel_ms": alt["sdf_ms"],
+                        "mfma_frac": flops / (alt["sdf_ms"] * 1e-3) / 1e12 / PEAK_TFLOPS["f16x2"],
+                        "speedup_vs_bf16x3": alt["rollout_steps_per_s"] / main_leg["rollout_steps_per_s"]}
     if not args.no_served and args.path == "fused" and args.workload == "paper" and not args.pe_freqs:
         out["served"] = served_leg(M, args.precision, args.served_requests)
     if not args.no_cpu:
