@@ -47,7 +47,8 @@ def _pair(seed_a, seed_b, inst):
     return a, hidden, explicit
 
 
-@pytest.mark.parametrize("path,precision,contract", [("plain", "fp32", "fp32"), ("fused", "bf16x3", "bf16w")])
+@pytest.mark.parametrize("path,precision,contract", [("plain", "fp32", "fp32"), ("fused", "bf16x3", "bf16w"),
+                                                     ("fused", "f16x2", "bf16w")])
 def test_unobserved_gate_uses_latest_observation(path, precision, contract):
     M = require_gpu()
     eng, w = _engine(M, path, precision)

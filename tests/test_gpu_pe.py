@@ -36,6 +36,7 @@ def _run(M, path, precision, layers, F, contract, probs):
     ("plain", "fp32", (0, 128, 128, 1), "fp32"),
     ("fused", "bf16x3", (0, 256, 256, 256, 1), "bf16w"),
     ("fused", "bf16x3", (0, 128, 128, 1), "bf16w"),
+    ("fused", "f16x2", (0, 256, 256, 256, 1), "bf16w"),
 ])
 def test_positional_encoding_parity(path, precision, layers, contract):
     M = require_gpu()

@@ -23,6 +23,7 @@ def _u0_error(u, ref):
     ("plain", "fp32", (67, 128, 128, 1), "fp32"),
     ("fused", "bf16x3", (67, 256, 256, 256, 1), "bf16w"),
     ("fused", "bf16x3", (67, 512, 512, 512, 1), "bf16w"),
+    ("fused", "f16x2", (67, 256, 256, 256, 1), "bf16w"),
 ])
 def test_rotor_rates_parity(path, precision, layers, contract):
     M = require_gpu()

@@ -53,11 +53,12 @@ def _mix(n, seed=7):
     return [dict(p, instance_id=1000 + i) for i, (_, p) in enumerate(reqs)]
 
 
-def test_alone_equals_mix_bitwise():
+@pytest.mark.parametrize("precision", ["bf16x3", "f16x2"])
+def test_alone_equals_mix_bitwise(precision):
     M = require_gpu()
     probs = _mix(24)
-    served, w = _engine(M)
-    alone, _ = _engine(M)
+    served, w = _engine(M, precision=precision)
+    alone, _ = _engine(M, precision=precision)
     tickets = []
     for p in probs:
         rc, t = served.submit(p)
@@ -65,7 +66,7 @@ def test_alone_equals_mix_bitwise():
         tickets.append(t)
     res = _wait(served, tickets, probs)
     st = served.stats()
-    say(f"served 24 uneven requests in {st['waves']} batches")
+    say(f"served {precision}: 24 uneven requests in {st['waves']} batches")
     for p, (rc, r) in zip(probs, res):
         assert rc == 0
         a = alone.step(p)
