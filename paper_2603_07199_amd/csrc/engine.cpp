@@ -827,7 +827,9 @@ int mppi_create(const mppi_config* cfg, const mppi_sdf_weights* w, mppi_engine**
     if (c.sdf_kind != MPPI_SDF_MLP || !fused_supported(c.precision, c.hidden, c.n_hidden)) return MPPI_EINVAL;
     const int max_tiles = (c.K_max + fused_tile_rollouts(c.precision, c.hidden, c.G_max) - 1) /
                           fused_tile_rollouts(c.precision, c.hidden, c.G_max);
-    if (fused_lds_bytes(c.precision, c.hidden, c.n_hidden, c.T_max, c.G_max, max_tiles) > kMaxLdsBytes) return MPPI_EINVAL;
+    const int feat_ks = c.pe_freqs > 0 ? (3 + 6 * c.pe_freqs + 3) / 4 : 0;   // layer-1 K-steps of the encoded point
+    if (fused_lds_bytes(c.precision, c.hidden, c.n_hidden, c.T_max, c.G_max, max_tiles, feat_ks) > kMaxLdsBytes)
+      return MPPI_EINVAL;
   }
   if (c.K_max < 1 || c.K_max > kMaxK || c.T_max < 1 || c.T_max > kMaxT || c.G_max < 1 || c.G_max > kMaxG)
     return MPPI_EINVAL;

@@ -46,7 +46,7 @@ int fused_tile_rollouts(int precision, int H, int G);
 // Whether the fused kernel exists for this precision / width / depth, and the
 // LDS bytes one workgroup needs for the given horizon, gate count and tiles.
 bool fused_supported(int precision, int H, int n_hidden);
-size_t fused_lds_bytes(int precision, int H, int n_hidden, int Tm, int Gm, int max_tiles);
+size_t fused_lds_bytes(int precision, int H, int n_hidden, int Tm, int Gm, int max_tiles, int feat_ks);
 constexpr size_t kMaxLdsBytes = 160 * 1024;
 
 // Quantise and pack the hidden H x H layers for a low-precision variant

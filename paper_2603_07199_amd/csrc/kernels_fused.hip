@@ -136,14 +136,14 @@ __host__ __device__ constexpr size_t act_buf_bytes() {
 }
 
 struct FusedLds {
-  size_t act, w1p, hb, wo, cf, rt, base, los, dp, hinge, pts, opart, jl, wt, fac, misc, xch, rot, total;
+  size_t act, w1p, hb, wo, cf, rt, base, los, dp, hinge, pts, opart, jl, wt, fac, misc, xch, rot, feat, total;
 };
 
 // The activation buffers (input of hidden layer l, block parity p) share
 // their space with the tile's control samples, which live only in the tile
 // prologue (dynamics) and epilogue (weighted sums), outside the decoder.
 template <int P, int H, int NHH>
-__host__ __device__ FusedLds fused_lds(int Tm, int Gm, int max_tiles) {
+__host__ __device__ FusedLds fused_lds(int Tm, int Gm, int max_tiles, int feat_ks = 0) {
   constexpr int WPL = kWaves / NHH;
   FusedLds L{};
   size_t o = 0;
@@ -169,6 +169,8 @@ __host__ __device__ FusedLds fused_lds(int Tm, int Gm, int max_tiles) {
   L.dp = take(sizeof(float) * 3 * kTileR * (Tm + 1));
   L.hinge = take(sizeof(float) * kTileR * Tm);
   L.fac = take(sizeof(double) * max_tiles);
+  // positional encoding: three slots of 4 feat_ks features x kRows rows
+  L.feat = take(sizeof(float) * 3 * 4 * feat_ks * kRows);
   L.total = o;
   return L;
 }
@@ -187,13 +189,14 @@ struct Views {
   char *act, *xch;
   float* rot;      // rotor-thrust-rate input: thrusts (4) and body rate (3) per rollout
   float *samp, *w1p, *hb, *wo, *cf, *rt, *base, *los, *dp, *hinge, *pts, *opart, *jl;
+  float* feat;     // encoded-point features of three blocks (positional encoding only)
   double *wt, *fac;
   int* misc;
 };
 
 template <int P, int H, int NHH>
-__device__ __forceinline__ Views make_views(char* lds, int Tm, int Gm, int max_tiles) {
-  const FusedLds L = fused_lds<P, H, NHH>(Tm, Gm, max_tiles);
+__device__ __forceinline__ Views make_views(char* lds, int Tm, int Gm, int max_tiles, int feat_ks = 0) {
+  const FusedLds L = fused_lds<P, H, NHH>(Tm, Gm, max_tiles, feat_ks);
   Views v{};
   v.act = lds + L.act;
   v.samp = (float*)(lds + L.act);
@@ -213,6 +216,7 @@ __device__ __forceinline__ Views make_views(char* lds, int Tm, int Gm, int max_t
   v.fac = (double*)(lds + L.fac);
   v.misc = (int*)(lds + L.misc);
   v.rot = (float*)(lds + L.rot);
+  v.feat = (float*)(lds + L.feat);
   return v;
 }
 
@@ -364,6 +368,52 @@ __device__ __forceinline__ void chunk_point(const Views& V, const EdgeConsts& e,
     pz = fmaf(R[6], dpp[0], fmaf(R[7], dpp[1], fmaf(R[8], dpp[2], b[2])));
   }
   *(float4*)out4 = make_float4(px, py, pz, (float)((e.p < e.Pc) ? e.g : 0));
+}
+
+// Coordinate comp of the gate-frame point of row r of block c, in the same
+// arithmetic as chunk_point (0 for a padding row).
+__device__ __forceinline__ float row_coord(const Views& V, const EdgeConsts& e, int c, int r, int comp) {
+  const int p = r / e.G, g = r - p * e.G;
+  const int q = c * e.Pc + p;
+  if (p >= e.Pc || q >= e.npos) return 0.0f;
+  const int kl = (int)(((float)q + 0.5f) * e.invT), t = q - kl * e.T;
+  const int tp = t + e.qoff;
+  const float* dpp = V.dp + 3 * (kl * (e.T + 1) + tp);
+  const float* R = V.rt + 9 * g + 3 * comp;
+  const float* b = V.base + 3 * (g * (e.T + 1) + tp);
+  return fmaf(R[0], dpp[0], fmaf(R[1], dpp[1], fmaf(R[2], dpp[2], b[comp])));
+}
+
+// Encoded-point features (Section III-B) of block c's rows into one slot of
+// the feature table, laid out as the layer-1 B operand: feature f of row r
+// at slot[f kRows + r], f = 3 + 6k + i the sine (i < 3) or cosine (i >= 3)
+// of pi 2^k times coordinate i mod 3, f < 3 the coordinates themselves.
+// Once per block for the whole workgroup: thread tid takes one raw
+// coordinate (tid < 3 kRows) or one (row, coordinate, frequency) item with
+// its sine and cosine; features past 3 + 6F stay at the zero they were
+// cleared to.
+__device__ __forceinline__ void pe_block(const Views& V, const EdgeConsts& e, int c, float* slot, int F, int tid) {
+  int r, comp, k = -1;
+  if (tid < 3 * kRows) {
+    r = tid / 3;
+    comp = tid - 3 * r;
+  } else {
+    const int j = tid - 3 * kRows;
+    if (j >= 3 * kRows * F) return;
+    r = j / (3 * F);
+    const int rem = j - r * 3 * F;
+    k = rem / 3;
+    comp = rem - 3 * k;
+  }
+  const float v = row_coord(V, e, c, r, comp);
+  if (k < 0) {
+    slot[comp * kRows + r] = v;
+  } else {
+    float sn, cs;
+    sincospif(ldexpf(v, k), &sn, &cs);
+    slot[(3 + 6 * k + comp) * kRows + r] = sn;
+    slot[(6 + 6 * k + comp) * kRows + r] = cs;
+  }
 }
 
 // Output of this lane's row of block c (lanes 0 .. kRows-1 of one wave): sum
@@ -623,12 +673,13 @@ template <int H> struct L1Split {
 };
 
 // PE (positional encoding, Section III-B): the point enters as PE(p); the
-// B operand of K-step ks is feature 4 ks + h of the row, computed in place,
-// and the A operands are W1's feature columns (fragments in global memory,
-// read through the caches: 52 KB at most).
+// B operand of K-step ks is feature 4 ks + h of the row from the block's
+// slot fs of the feature table, and the A operands are W1's feature columns
+// (fragments in global memory, read through the caches: 52 KB at most).
 template <int H, int NB, bool PE>
-__device__ __forceinline__ void layer1_products(const float* pts, const float* cf, const float* w1p, int b0, int h,
-                                                int nl, f32x4 (&x)[NB > 0 ? NB : 1], const DeviceWeights& w) {
+__device__ __forceinline__ void layer1_products(const float* pts, const float* fs, const float* cf, const float* w1p,
+                                                int b0, int h, int nl, f32x4 (&x)[NB > 0 ? NB : 1],
+                                                const DeviceWeights& w) {
   const int g = (int)pts[4 * nl + 3];
   if constexpr (!PE) {
     const float bk = pts[4 * nl + h];
@@ -644,10 +695,9 @@ __device__ __forceinline__ void layer1_products(const float* pts, const float* c
       const float4 c4 = *(const float4*)(cf + g * H + 16 * (b0 + j) + 4 * h);
       x[j] = f32x4{c4.x, c4.y, c4.z, c4.w};
     }
-    const float px = pts[4 * nl], py = pts[4 * nl + 1], pz = pts[4 * nl + 2];
     const int KQ = w.feat_ksteps, lane = 16 * h + nl;
     for (int ks = 0; ks < KQ; ++ks) {
-      const float bk = pe_feature(4 * ks + h, px, py, pz, w.pe_freqs);
+      const float bk = fs[(4 * ks + h) * kRows + nl];
 #pragma unroll
       for (int j = 0; j < NB; ++j)
         x[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(w.w1pe[((size_t)(b0 + j) * KQ + ks) * 64 + lane], bk, x[j], 0, 0, 0);
@@ -708,6 +758,7 @@ template <int P, int H, int NHH, int OWN, int PAR, bool MFIRST, int MB, bool PE>
 __device__ __forceinline__ void pipeline_step(const Views& V, const DeviceWeights& w, int wave, int gw, int h,
                                               int nl, float scale_own, const FragT<P> (&wreg)[MB][H / 32],
                                               f32x4 (&acc)[2][MB], const float* pts_prev, const float* pts_cur,
+                                              const float* fs_prev, const float* fs_cur,
                                               f32x4 (&x1c)[L1Split<H>::A > 0 ? L1Split<H>::A : 1]) {
   constexpr int WPL = kWaves / NHH;
   constexpr size_t AB = act_buf_bytes<P, H>();
@@ -725,7 +776,7 @@ __device__ __forceinline__ void pipeline_step(const Views& V, const DeviceWeight
     f32x4 x1[NB > 0 ? NB : 1];
     read_operands<P, H>(in, boff, 0, b0);
     products<P, H, OWN, MB>(in, boff, V.hb, gw, h, wreg, b0, acc[PAR]);
-    layer1_products<H, NB, PE>(pts_prev, V.cf, V.w1p, l1b, h, nl, x1, w);
+    layer1_products<H, NB, PE>(pts_prev, fs_prev, V.cf, V.w1p, l1b, h, nl, x1, w);
     sched_fence();
     vector_work<P, H, NHH, OWN, MB, NB>(acc[1 - PAR], x1, out, l1out, op, V.hb, V.wo, w, l1b, gw, h, nl, scale_own);
   } else {
@@ -738,7 +789,7 @@ __device__ __forceinline__ void pipeline_step(const Views& V, const DeviceWeight
     vector_work<P, H, NHH, OWN, MB, NB>(acc[1 - PAR], x1c, out, l1out, op, V.hb, V.wo, w, l1b, gw, h, nl, scale_own);
     sched_fence();
     products<P, H, OWN, MB>(in, boff, V.hb, gw, h, wreg, b0, acc[PAR]);
-    layer1_products<H, NB, PE>(pts_cur, V.cf, V.w1p, l1b, h, nl, x1c, w);
+    layer1_products<H, NB, PE>(pts_cur, fs_cur, V.cf, V.w1p, l1b, h, nl, x1c, w);
   }
 }
 
@@ -764,18 +815,24 @@ __device__ __forceinline__ void decoder_tile(const Views& V, const SolveDesc& d,
   // block s+1 while the layer-1 products read blocks s-1 and s.  The edge
   // work goes to two waves that run their vector work first and have slack at
   // the barrier (the products-first waves do not).
+  // With the positional encoding every thread also forms its share of the
+  // features of block s+1 in step s, into feature slot (s+1) % 3.
   const EdgeConsts ec = edge_consts(d, lane, npos, w.bout);
+  const int fslot = 4 * w.feat_ksteps * kRows;
   if (wave == 1 && lane < kRows) chunk_point(V, ec, 0, V.pts + 4 * lane);
+  if constexpr (PE) pe_block(V, ec, 0, V.feat, w.pe_freqs, 64 * wave + lane);
   __syncthreads();
   int slot = 0;                       // = s % 3
   auto edges = [&](int st, int par) {
     const int nxt = slot == 2 ? 0 : slot + 1;
     if (wave == 1 && lane < kRows) chunk_point(V, ec, st + 1, V.pts + 4 * (nxt * kRows + lane));
+    if constexpr (PE) pe_block(V, ec, st + 1, V.feat + nxt * fslot, w.pe_freqs, 64 * wave + lane);
     const int br = st - lag;
     if (wave == 2 && lane < kRows && br >= 0 && br < nblk)
       chunk_reduce<WPL>(V, ec, V.opart + par * WPL * kRows * 4, br, lane);
   };
   auto slot_pts = [&](int sl) { return V.pts + 4 * kRows * sl; };
+  auto slot_fs = [&](int sl) { return V.feat + fslot * sl; };
   for (int s = 0; s < nsteps; s += 2) {
     // the lane indices pass through an empty asm each step, so the compiler
     // recomputes the lane's LDS addresses inside the step (a few adds)
@@ -784,13 +841,15 @@ __device__ __forceinline__ void decoder_tile(const Views& V, const SolveDesc& d,
     asm volatile("" : "+v"(hv), "+v"(nv));
     edges(s, 0);
     pipeline_step<P, H, NHH, OWN, 0, MFIRST, MB, PE>(V, w, wave, gw, hv, nv, scale_own, wreg, acc,
-                                                 slot_pts(slot == 0 ? 2 : slot - 1), slot_pts(slot), x1c);
+                                                 slot_pts(slot == 0 ? 2 : slot - 1), slot_pts(slot),
+                                                 slot_fs(slot == 0 ? 2 : slot - 1), slot_fs(slot), x1c);
     __syncthreads();
     slot = slot == 2 ? 0 : slot + 1;
     asm volatile("" : "+v"(hv), "+v"(nv));
     edges(s + 1, 1);
     pipeline_step<P, H, NHH, OWN, 1, MFIRST, MB, PE>(V, w, wave, gw, hv, nv, scale_own, wreg, acc,
-                                                 slot_pts(slot == 0 ? 2 : slot - 1), slot_pts(slot), x1c);
+                                                 slot_pts(slot == 0 ? 2 : slot - 1), slot_pts(slot),
+                                                 slot_fs(slot == 0 ? 2 : slot - 1), slot_fs(slot), x1c);
     __syncthreads();
     slot = slot == 2 ? 0 : slot + 1;
   }
@@ -804,10 +863,13 @@ __global__ __launch_bounds__(kThreads, 1) void k_fused(FusedBatch batch, DeviceW
   constexpr int MB = H / WPL / 16;    // 16-neuron blocks per wave
   constexpr int KS = H / 32;          // K-steps of 32
   extern __shared__ __align__(16) char lds[];
-  const Views V = make_views<P, H, NHH>(lds, Tm, Gm, max_tiles);
+  const Views V = make_views<P, H, NHH>(lds, Tm, Gm, max_tiles, PE ? w.feat_ksteps : 0);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int h = lane >> 4, nl = lane & 15;
   const int own = wave / WPL, gw = wave % WPL;
+  // feature table: padding features (past 3 + 6F) must read as zero
+  if constexpr (PE)
+    for (int i = tid; i < 3 * 4 * w.feat_ksteps * kRows; i += kThreads) V.feat[i] = 0.0f;
 
   // ---- weights of the owned neurons, resident in VGPRs for the whole kernel
   FragT<P> wreg[MB][KS];
@@ -1358,7 +1420,7 @@ __global__ __launch_bounds__(kWideThreads, 1) void k_wide(FusedBatch batch, Devi
 template <int P, int H, int NHH, bool PE>
 static hipError_t launch_fused_t(const FusedBatch& b, const DeviceWeights& w, int Tm, int Gm,
                                  int max_tiles, hipStream_t s) {
-  const FusedLds L = fused_lds<P, H, NHH>(Tm, Gm, max_tiles);
+  const FusedLds L = fused_lds<P, H, NHH>(Tm, Gm, max_tiles, PE ? w.feat_ksteps : 0);
   {
     // raise the kernel's dynamic LDS limit to the largest size launched so far
     // (engines on several threads may launch the same instantiation)
@@ -1452,14 +1514,16 @@ bool fused_supported(int precision, int H, int n_hidden) {
   return (H == 128 || H == 256 || H == 512) && (n_hidden == 2 || n_hidden == 3);
 }
 
-size_t fused_lds_bytes(int precision, int H, int n_hidden, int Tm, int Gm, int max_tiles) {
+size_t fused_lds_bytes(int precision, int H, int n_hidden, int Tm, int Gm, int max_tiles, int feat_ks) {
   auto pick = [&](auto p_tag) -> size_t {
     constexpr int P = decltype(p_tag)::value;
     if (H == 512)
       return n_hidden == 2 ? wide_lds<P, 512, 1>(Tm, Gm, max_tiles).total : wide_lds<P, 512, 2>(Tm, Gm, max_tiles).total;
     if (n_hidden == 2)
-      return H == 128 ? fused_lds<P, 128, 1>(Tm, Gm, max_tiles).total : fused_lds<P, 256, 1>(Tm, Gm, max_tiles).total;
-    return H == 128 ? fused_lds<P, 128, 2>(Tm, Gm, max_tiles).total : fused_lds<P, 256, 2>(Tm, Gm, max_tiles).total;
+      return H == 128 ? fused_lds<P, 128, 1>(Tm, Gm, max_tiles, feat_ks).total
+                      : fused_lds<P, 256, 1>(Tm, Gm, max_tiles, feat_ks).total;
+    return H == 128 ? fused_lds<P, 128, 2>(Tm, Gm, max_tiles, feat_ks).total
+                    : fused_lds<P, 256, 2>(Tm, Gm, max_tiles, feat_ks).total;
   };
   switch (precision) {
     case P_BF16: return pick(std::integral_constant<int, P_BF16>{});
