@@ -703,7 +703,8 @@ int upload_weights(mppi_engine* e, const mppi_sdf_weights* w) {
   std::vector<float> w1p((size_t)H * 4, 0.0f), hbias((size_t)nh * H, 0.0f), wout(H, 0.0f);
   std::vector<double> w0lat((size_t)H * D, 0.0), b0(H, 0.0);
   std::vector<float> hf32;
-  std::vector<uint8_t> hlp;
+  std::vector<uint8_t> hlp, pe16;
+  float pe16_scale = 1.0f;
   std::vector<float> wsc(nh, 1.0f), asc(nh, 1.0f), ainv(nh, 1.0f);
   float bout = 0.0f;
   if (mlp) {
@@ -738,6 +739,7 @@ int upload_weights(mppi_engine* e, const mppi_sdf_weights* w) {
     if (e->fused) {
       int rc = pack_lowp_weights(e->cfg.precision, H, L, w, hlp, wsc, asc, ainv);
       if (rc != MPPI_OK) return rc;
+      if (KQ > 0) pack_pe_weights_f16(H, NF, NF + D, w->W[0], pe16, pe16_scale);
     }
   }
   const uint64_t o_w1p = 0;
@@ -751,7 +753,8 @@ int upload_weights(mppi_engine* e, const mppi_sdf_weights* w) {
   const uint64_t o_as = align_up(o_ws + 4 * wsc.size());
   const uint64_t o_ai = align_up(o_as + 4 * asc.size());
   const uint64_t o_pe = align_up(o_ai + 4 * ainv.size());
-  const uint64_t total = align_up(o_pe + 4 * w1pe.size());
+  const uint64_t o_p16 = align_up(o_pe + 4 * w1pe.size());
+  const uint64_t total = align_up(o_p16 + pe16.size());
   HIPCHK(e, hipMalloc(&e->wmem, total));
   char* b = (char*)e->wmem;
   HIPCHK(e, hipMemcpy(b + o_w1p, w1p.data(), 4 * w1p.size(), hipMemcpyHostToDevice));
@@ -765,6 +768,7 @@ int upload_weights(mppi_engine* e, const mppi_sdf_weights* w) {
   HIPCHK(e, hipMemcpy(b + o_as, asc.data(), 4 * asc.size(), hipMemcpyHostToDevice));
   HIPCHK(e, hipMemcpy(b + o_ai, ainv.data(), 4 * ainv.size(), hipMemcpyHostToDevice));
   if (!w1pe.empty()) HIPCHK(e, hipMemcpy(b + o_pe, w1pe.data(), 4 * w1pe.size(), hipMemcpyHostToDevice));
+  if (!pe16.empty()) HIPCHK(e, hipMemcpy(b + o_p16, pe16.data(), pe16.size(), hipMemcpyHostToDevice));
   DeviceWeights& dw = e->dw;
   dw.H = H;
   dw.n_hidden = L;
@@ -784,6 +788,9 @@ int upload_weights(mppi_engine* e, const mppi_sdf_weights* w) {
   dw.n_feat = NF;
   dw.feat_ksteps = KQ;
   dw.w1pe = w1pe.empty() ? nullptr : (const float*)(b + o_pe);
+  dw.feat_k32 = KQ > 0 ? (NF + 31) / 32 : 0;
+  dw.w1pe_scale = pe16_scale;
+  dw.w1pe16 = pe16.empty() ? nullptr : (const void*)(b + o_p16);
   return MPPI_OK;
 }
 
@@ -827,7 +834,7 @@ int mppi_create(const mppi_config* cfg, const mppi_sdf_weights* w, mppi_engine**
     if (c.sdf_kind != MPPI_SDF_MLP || !fused_supported(c.precision, c.hidden, c.n_hidden)) return MPPI_EINVAL;
     const int max_tiles = (c.K_max + fused_tile_rollouts(c.precision, c.hidden, c.G_max) - 1) /
                           fused_tile_rollouts(c.precision, c.hidden, c.G_max);
-    const int feat_ks = c.pe_freqs > 0 ? (3 + 6 * c.pe_freqs + 3) / 4 : 0;   // layer-1 K-steps of the encoded point
+    const int feat_ks = c.pe_freqs > 0 ? (3 + 6 * c.pe_freqs + 31) / 32 : 0;   // 32-wide K-steps of the encoded point
     if (fused_lds_bytes(c.precision, c.hidden, c.n_hidden, c.T_max, c.G_max, max_tiles, feat_ks) > kMaxLdsBytes)
       return MPPI_EINVAL;
   }

@@ -52,6 +52,8 @@ constexpr size_t kMaxLdsBytes = 160 * 1024;
 // Quantise and pack the hidden H x H layers for a low-precision variant
 // (BF16, BF16X2, FP8) in the fused kernel's operand order.  Returns an
 // mppi_status.
+// Encoded-point columns of layer 0 for the fused decoder (see DeviceWeights).
+void pack_pe_weights_f16(int H, int n_feat, int ld, const float* W0, std::vector<uint8_t>& blob, float& scale);
 int pack_lowp_weights(int precision, int H, int n_hidden, const mppi_sdf_weights* w,
                       std::vector<uint8_t>& blob, std::vector<float>& w_scale,
                       std::vector<float>& a_scale, std::vector<float>& a_inv);

@@ -135,6 +135,12 @@ __host__ __device__ constexpr size_t act_buf_bytes() {
                             : (size_t)PrecTraits<P>::splits * kRows * act_stride_bf16<H>() * 2;
 }
 
+// Feature table of one block for the encoded-point layer 1: two FP16 terms
+// (hi, lo) of every feature, per term kRows rows of 32 k32 features plus a
+// pad of 8 (16-byte operand reads of 16 rows on distinct banks).
+__host__ __device__ constexpr int pe_row_halves(int k32) { return 32 * k32 + 8; }
+__host__ __device__ constexpr size_t pe_slot_bytes(int k32) { return (size_t)2 * kRows * pe_row_halves(k32) * 2; }
+
 struct FusedLds {
   size_t act, w1p, hb, wo, cf, rt, base, los, dp, hinge, pts, opart, jl, wt, fac, misc, xch, rot, feat, total;
 };
@@ -169,8 +175,8 @@ __host__ __device__ FusedLds fused_lds(int Tm, int Gm, int max_tiles, int feat_k
   L.dp = take(sizeof(float) * 3 * kTileR * (Tm + 1));
   L.hinge = take(sizeof(float) * kTileR * Tm);
   L.fac = take(sizeof(double) * max_tiles);
-  // positional encoding: three slots of 4 feat_ks features x kRows rows
-  L.feat = take(sizeof(float) * 3 * 4 * feat_ks * kRows);
+  // positional encoding: three slots of the FP16 feature table
+  L.feat = take(pe_slot_bytes(feat_ks) * 3);
   L.total = o;
   return L;
 }
@@ -189,7 +195,7 @@ struct Views {
   char *act, *xch;
   float* rot;      // rotor-thrust-rate input: thrusts (4) and body rate (3) per rollout
   float *samp, *w1p, *hb, *wo, *cf, *rt, *base, *los, *dp, *hinge, *pts, *opart, *jl;
-  float* feat;     // encoded-point features of three blocks (positional encoding only)
+  char* feat;      // encoded-point features of three blocks (positional encoding only)
   double *wt, *fac;
   int* misc;
 };
@@ -216,7 +222,7 @@ __device__ __forceinline__ Views make_views(char* lds, int Tm, int Gm, int max_t
   v.fac = (double*)(lds + L.fac);
   v.misc = (int*)(lds + L.misc);
   v.rot = (float*)(lds + L.rot);
-  v.feat = (float*)(lds + L.feat);
+  v.feat = lds + L.feat;
   return v;
 }
 
@@ -385,14 +391,20 @@ __device__ __forceinline__ float row_coord(const Views& V, const EdgeConsts& e, 
 }
 
 // Encoded-point features (Section III-B) of block c's rows into one slot of
-// the feature table, laid out as the layer-1 B operand: feature f of row r
-// at slot[f kRows + r], f = 3 + 6k + i the sine (i < 3) or cosine (i >= 3)
-// of pi 2^k times coordinate i mod 3, f < 3 the coordinates themselves.
-// Once per block for the whole workgroup: thread tid takes one raw
-// coordinate (tid < 3 kRows) or one (row, coordinate, frequency) item with
-// its sine and cosine; features past 3 + 6F stay at the zero they were
-// cleared to.
-__device__ __forceinline__ void pe_block(const Views& V, const EdgeConsts& e, int c, float* slot, int F, int tid) {
+// the feature table: feature f = 3 + 6k + i is the sine (i < 3) or cosine
+// (i >= 3) of pi 2^k times coordinate i mod 3, f < 3 the coordinates
+// themselves; each is stored as hi = its RNE half and lo = the RNE half of
+// the remainder, at [term][row][f] (row stride pe_row_halves).  Once per
+// block for the whole workgroup: thread tid takes one raw coordinate
+// (tid < 3 kRows) or one (row, coordinate, frequency) item with its sine and
+// cosine; features past 3 + 6F stay at the zero they were cleared to.
+__device__ __forceinline__ void put_feature(_Float16* t, int stride, int r, int f, float v) {
+  const _Float16 hi = (_Float16)v;
+  t[r * stride + f] = hi;
+  t[kRows * stride + r * stride + f] = (_Float16)(v - (float)hi);
+}
+__device__ __forceinline__ void pe_block(const Views& V, const EdgeConsts& e, int c, char* slot, int F, int k32,
+                                         int tid) {
   int r, comp, k = -1;
   if (tid < 3 * kRows) {
     r = tid / 3;
@@ -406,13 +418,15 @@ __device__ __forceinline__ void pe_block(const Views& V, const EdgeConsts& e, in
     comp = rem - 3 * k;
   }
   const float v = row_coord(V, e, c, r, comp);
+  _Float16* t = (_Float16*)slot;
+  const int stride = pe_row_halves(k32);
   if (k < 0) {
-    slot[comp * kRows + r] = v;
+    put_feature(t, stride, r, comp, v);
   } else {
     float sn, cs;
     sincospif(ldexpf(v, k), &sn, &cs);
-    slot[(3 + 6 * k + comp) * kRows + r] = sn;
-    slot[(6 + 6 * k + comp) * kRows + r] = cs;
+    put_feature(t, stride, r, 3 + 6 * k + comp, sn);
+    put_feature(t, stride, r, 6 + 6 * k + comp, cs);
   }
 }
 
@@ -672,12 +686,16 @@ template <int H> struct L1Split {
   __device__ static int first(int wave) { return wave >= kWaves / 2 ? (wave - kWaves / 2) * B : (kWaves / 2) * B + wave * A; }
 };
 
-// PE (positional encoding, Section III-B): the point enters as PE(p); the
-// B operand of K-step ks is feature 4 ks + h of the row from the block's
-// slot fs of the feature table, and the A operands are W1's feature columns
-// (fragments in global memory, read through the caches: 52 KB at most).
+// PE (positional encoding, Section III-B): the point enters as PE(p), a
+// product over K = 32 feat_k32 features on FP16 matrix cores with both
+// operands split in two terms, W1' = W1 / scale = Wh + Wl and f = fh + fl:
+// Wh fh + Wh fl + Wl fh (the dropped Wl fl and the term roundings leave
+// ~2^-21 of |W1| |f| per feature).  The B operands come from the block's
+// slot fs of the feature table, the A operands are fragments in global
+// memory read through the caches (26 KB at H = 256); the accumulators start
+// at the folded latent term / scale and end times scale (exact powers of 2).
 template <int H, int NB, bool PE>
-__device__ __forceinline__ void layer1_products(const float* pts, const float* fs, const float* cf, const float* w1p,
+__device__ __forceinline__ void layer1_products(const float* pts, const char* fs, const float* cf, const float* w1p,
                                                 int b0, int h, int nl, f32x4 (&x)[NB > 0 ? NB : 1],
                                                 const DeviceWeights& w) {
   const int g = (int)pts[4 * nl + 3];
@@ -690,18 +708,30 @@ __device__ __forceinline__ void layer1_products(const float* pts, const float* f
       x[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(w1p[4 * (16 * (b0 + j) + nl) + h], bk, x[j], 0, 0, 0);
     }
   } else {
+    const float sc = w.w1pe_scale, up = 1.0f / sc;
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
       const float4 c4 = *(const float4*)(cf + g * H + 16 * (b0 + j) + 4 * h);
-      x[j] = f32x4{c4.x, c4.y, c4.z, c4.w};
+      x[j] = f32x4{c4.x * up, c4.y * up, c4.z * up, c4.w * up};
     }
-    const int KQ = w.feat_ksteps, lane = 16 * h + nl;
-    for (int ks = 0; ks < KQ; ++ks) {
-      const float bk = fs[(4 * ks + h) * kRows + nl];
+    const int K32 = w.feat_k32, lane = 16 * h + nl, stride = pe_row_halves(K32);
+    const uint4* wf = (const uint4*)w.w1pe16;
+    for (int ks = 0; ks < K32; ++ks) {
+      const char* rb = fs + (size_t)(nl * stride + 32 * ks + 8 * h) * 2;
+      const f16x8 fh = __builtin_bit_cast(f16x8, *(const uint4*)rb);
+      const f16x8 fl = __builtin_bit_cast(f16x8, *(const uint4*)(rb + (size_t)kRows * stride * 2));
 #pragma unroll
-      for (int j = 0; j < NB; ++j)
-        x[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(w.w1pe[((size_t)(b0 + j) * KQ + ks) * 64 + lane], bk, x[j], 0, 0, 0);
+      for (int j = 0; j < NB; ++j) {
+        const size_t fi = (((size_t)(b0 + j) * K32 + ks) * 2) * 64 + lane;
+        const f16x8 wh = __builtin_bit_cast(f16x8, wf[fi]);
+        const f16x8 wl = __builtin_bit_cast(f16x8, wf[fi + 64]);
+        x[j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(wh, fh, x[j], 0, 0, 0);
+        x[j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(wh, fl, x[j], 0, 0, 0);
+        x[j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(wl, fh, x[j], 0, 0, 0);
+      }
     }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) x[j] = x[j] * sc;
   }
 }
 
@@ -758,7 +788,7 @@ template <int P, int H, int NHH, int OWN, int PAR, bool MFIRST, int MB, bool PE>
 __device__ __forceinline__ void pipeline_step(const Views& V, const DeviceWeights& w, int wave, int gw, int h,
                                               int nl, float scale_own, const FragT<P> (&wreg)[MB][H / 32],
                                               f32x4 (&acc)[2][MB], const float* pts_prev, const float* pts_cur,
-                                              const float* fs_prev, const float* fs_cur,
+                                              const char* fs_prev, const char* fs_cur,
                                               f32x4 (&x1c)[L1Split<H>::A > 0 ? L1Split<H>::A : 1]) {
   constexpr int WPL = kWaves / NHH;
   constexpr size_t AB = act_buf_bytes<P, H>();
@@ -818,15 +848,15 @@ __device__ __forceinline__ void decoder_tile(const Views& V, const SolveDesc& d,
   // With the positional encoding every thread also forms its share of the
   // features of block s+1 in step s, into feature slot (s+1) % 3.
   const EdgeConsts ec = edge_consts(d, lane, npos, w.bout);
-  const int fslot = 4 * w.feat_ksteps * kRows;
+  const size_t fslot = pe_slot_bytes(w.feat_k32);
   if (wave == 1 && lane < kRows) chunk_point(V, ec, 0, V.pts + 4 * lane);
-  if constexpr (PE) pe_block(V, ec, 0, V.feat, w.pe_freqs, 64 * wave + lane);
+  if constexpr (PE) pe_block(V, ec, 0, V.feat, w.pe_freqs, w.feat_k32, 64 * wave + lane);
   __syncthreads();
   int slot = 0;                       // = s % 3
   auto edges = [&](int st, int par) {
     const int nxt = slot == 2 ? 0 : slot + 1;
     if (wave == 1 && lane < kRows) chunk_point(V, ec, st + 1, V.pts + 4 * (nxt * kRows + lane));
-    if constexpr (PE) pe_block(V, ec, st + 1, V.feat + nxt * fslot, w.pe_freqs, 64 * wave + lane);
+    if constexpr (PE) pe_block(V, ec, st + 1, V.feat + nxt * fslot, w.pe_freqs, w.feat_k32, 64 * wave + lane);
     const int br = st - lag;
     if (wave == 2 && lane < kRows && br >= 0 && br < nblk)
       chunk_reduce<WPL>(V, ec, V.opart + par * WPL * kRows * 4, br, lane);
@@ -863,13 +893,13 @@ __global__ __launch_bounds__(kThreads, 1) void k_fused(FusedBatch batch, DeviceW
   constexpr int MB = H / WPL / 16;    // 16-neuron blocks per wave
   constexpr int KS = H / 32;          // K-steps of 32
   extern __shared__ __align__(16) char lds[];
-  const Views V = make_views<P, H, NHH>(lds, Tm, Gm, max_tiles, PE ? w.feat_ksteps : 0);
+  const Views V = make_views<P, H, NHH>(lds, Tm, Gm, max_tiles, PE ? w.feat_k32 : 0);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int h = lane >> 4, nl = lane & 15;
   const int own = wave / WPL, gw = wave % WPL;
   // feature table: padding features (past 3 + 6F) must read as zero
   if constexpr (PE)
-    for (int i = tid; i < 3 * 4 * w.feat_ksteps * kRows; i += kThreads) V.feat[i] = 0.0f;
+    for (int i = tid; i < (int)(3 * pe_slot_bytes(w.feat_k32) / 4); i += kThreads) ((uint32_t*)V.feat)[i] = 0u;
 
   // ---- weights of the owned neurons, resident in VGPRs for the whole kernel
   FragT<P> wreg[MB][KS];
@@ -1420,7 +1450,7 @@ __global__ __launch_bounds__(kWideThreads, 1) void k_wide(FusedBatch batch, Devi
 template <int P, int H, int NHH, bool PE>
 static hipError_t launch_fused_t(const FusedBatch& b, const DeviceWeights& w, int Tm, int Gm,
                                  int max_tiles, hipStream_t s) {
-  const FusedLds L = fused_lds<P, H, NHH>(Tm, Gm, max_tiles, PE ? w.feat_ksteps : 0);
+  const FusedLds L = fused_lds<P, H, NHH>(Tm, Gm, max_tiles, PE ? w.feat_k32 : 0);
   {
     // raise the kernel's dynamic LDS limit to the largest size launched so far
     // (engines on several threads may launch the same instantiation)
@@ -1557,6 +1587,35 @@ static uint16_t host_f16_rne(float x) {
   const int E = e - 1 + 15;
   if (E >= 31) return sign | 0x7BFF;
   return sign | (uint16_t)((E << 10) | ((int)q - 1024));
+}
+
+static float host_f16_to_float(uint16_t h) {
+  const int e = (h >> 10) & 31, m = h & 1023;
+  const double v = e == 0 ? ldexp((double)m, -24) : ldexp((double)(1024 + m), e - 25);
+  return (float)((h & 0x8000) ? -v : v);
+}
+
+void pack_pe_weights_f16(int H, int n_feat, int ld, const float* W0, std::vector<uint8_t>& blob, float& scale) {
+  const int K32 = (n_feat + 31) / 32;
+  float amax = 0.0f;
+  for (int m = 0; m < H; ++m)
+    for (int f = 0; f < n_feat; ++f) amax = std::max(amax, fabsf(W0[(size_t)m * ld + f]));
+  int e = 0;
+  if (amax > 0.0f) frexpf(amax, &e);      // amax in [2^(e-1), 2^e): amax / scale < 2^15
+  scale = amax > 0.0f ? ldexpf(1.0f, e - 15) : 1.0f;
+  blob.assign((size_t)(H / 16) * K32 * 2 * 64 * 16, 0);
+  for (int mb = 0; mb < H / 16; ++mb)
+    for (int ks = 0; ks < K32; ++ks)
+      for (int lane = 0; lane < 64; ++lane)
+        for (int j = 0; j < 8; ++j) {
+          const int m = 16 * mb + lane % 16, f = 32 * ks + 8 * (lane / 16) + j;
+          const float v = f < n_feat ? W0[(size_t)m * ld + f] / scale : 0.0f;
+          const uint16_t hi = host_f16_rne(v);
+          const uint16_t lo = host_f16_rne(v - host_f16_to_float(hi));
+          const size_t fi = (((size_t)mb * K32 + ks) * 2) * 64 + lane;
+          memcpy(&blob[fi * 16 + 2 * j], &hi, 2);
+          memcpy(&blob[(fi + 64) * 16 + 2 * j], &lo, 2);
+        }
 }
 
 // OCP E4M3 (bias 7, max 448, no infinities), round to nearest even, saturating.

@@ -30,6 +30,12 @@ struct DeviceWeights {
   // [H/16][feat_ksteps][64] = W1[16 mb + lane % 16][4 ks + lane / 16] (0 past n_feat)
   int pe_freqs, n_feat, feat_ksteps;
   const float* w1pe;
+  // the same columns for the fused decoder as FP16 16x16x32 A fragments of
+  // W1 / w1pe_scale split into two terms, [H/16][feat_k32][2][64] x 8 halves
+  // = term of W1[16 mb + lane % 16][32 ks + 8 (lane / 16) + j] (0 past n_feat)
+  int feat_k32;
+  float w1pe_scale;
+  const void* w1pe16;
 };
 
 }  // namespace mppi
