@@ -65,7 +65,7 @@ typedef enum mppi_precision {
   MPPI_PREC_BF16X3 = 4, /* BF16 weights, activations split hi + mid + lo in BF16 (three products) */
   MPPI_PREC_F16X2 = 5   /* BF16-rounded weights held exactly in FP16 (per-layer power-of-two scale),
                            activations split hi + lo in FP16 (two products); activations are
-                           capped at 65504 */
+                           capped at 65503 */
 } mppi_precision;
 
 typedef enum mppi_path {
