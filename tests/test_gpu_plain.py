@@ -13,6 +13,7 @@ import pytest
 
 import oracle
 import scenarios as sc
+from oracle.mppi import sample_controls
 from gpu_common import U0_TOL, require_gpu, say, seq_error, u0_error
 
 pytestmark = pytest.mark.gpu
@@ -65,6 +66,28 @@ def test_p1_elementwise_and_u0(p1, d_safe):
         assert abs(out["ess"] - ref["ess"]) <= 1e-3 * ref["ess"]
     say(f"P1 d_safe={d_safe}: u0 errors {['%.2e' % e for e in errs]}")
     assert max(errs) <= U0_TOL
+
+
+def test_noise_stream_at_scale():
+    """The device's Philox4x64-10 stream and its Box-Muller transform against
+    the oracle's over 1.47 M counters (K = 8192, T = 60, three ticks, with a
+    64-bit key and an instance id and tick that set high counter bits): the
+    samples use the top 24 bits of every Philox word, so any word that
+    differs moves a sample far outside the float32 tolerance."""
+    M = require_gpu()
+    key = 0x9E3779B97F4A7C15          # the engine's Philox key (mppi_config.seed)
+    eng, _ = _engine(M, (67, 128, 128, 1), 8192, 60, 1, budget=1 << 30, seed=key)
+    U = oracle.hover_sequence(60, sc.MODEL["mass"], sc.MODEL["gravity"])
+    for tick in (0, 1, 0xFFFFFFFE):
+        prob = sc.make_problem(8192, 60, 1, seed=3, instance_id=(1 << 40) + 7, tick=tick, rng_seed=key,
+                               U_nom=U)
+        out = eng.step(prob, exports=True)
+        assert out["rc"] == 0
+        ref = sample_controls(prob, sc.MODEL, U)
+        _within("samples", out["samples"], ref, 2e-6 * (np.abs(ref) + 1.0))
+        say(f"noise stream tick {tick:#x}: {ref.size // 4} counters, max |du| "
+            f"{np.abs(out['samples'] - ref).max():.1e}")
+    eng.close()
 
 
 def test_p1_32_scenarios_u0_error(p1):
