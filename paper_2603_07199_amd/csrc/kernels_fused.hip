@@ -954,23 +954,27 @@ __global__ void k_fused_prep(FusedBatch b) {
   if (blockIdx.x == 0 && threadIdx.x == 0) *b.tile_counter = 0u;
 }
 
-constexpr int kMergeThreads = 256;
+constexpr int kMergeThreads = 1024;
+constexpr int kMergeChunks = 4;      // tile ranges of the U* sums
 
 // Merge of one solve's tile partials (workgroup = solve; runs after the fused
 // kernel, whose completion makes every partial visible):
 //   rho = min_i rho_i, f_i = exp(-(rho_i - rho) / lambda),
 //   eta = sum_i eta_i f_i, U*[t][c] = sum_i S_i[t][c] f_i / eta,
 // then the normalised weights, the warm start, the tick and the scalars.
-// Every sum runs in an order fixed by the tile index, so the result does not
-// depend on which workgroup ran which tile or on what else was in the batch.
+// Every sum runs in an order fixed by the tile index (U*: kMergeChunks
+// consecutive tile ranges, each summed in order, then the ranges in order),
+// so the result does not depend on which workgroup ran which tile or on what
+// else was in the batch.
 __global__ __launch_bounds__(kMergeThreads) void k_fused_merge(FusedBatch batch) {
   extern __shared__ __align__(16) char lds[];
   constexpr int NW = kMergeThreads / 64;
-  double* red = (double*)lds;          // 3 NW per-wave partial results
-  double* fac = red + 3 * NW;          // n tile factors
   const SolveDesc& d = batch.descs[blockIdx.x];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int n = d.n_tiles, T = d.T, K = d.K;
+  double* red = (double*)lds;          // 3 NW per-wave partial results
+  double* part = red + 3 * NW;         // kMergeChunks x 4T partial sums of U*
+  double* fac = part + kMergeChunks * 4 * T;   // n tile factors
   const uint32_t tick = d.tick_fixed == 0xFFFFFFFFu ? *d.tick_slot : d.tick_fixed;
   // rho = min over tiles with weight (min is exact in any order)
   double r = INFINITY;
@@ -1009,14 +1013,24 @@ __global__ __launch_bounds__(kMergeThreads) void k_fused_merge(FusedBatch batch)
   }
   const bool ok = isfinite(rho) && eta > 0.0;
   double* res = d.result;
-  // U*[t][c]: one thread per output, tiles in index order
+  // U*[t][c]: partial sums over kMergeChunks tile ranges, each in tile order
+  if (ok)
+    for (int i = tid; i < kMergeChunks * 4 * T; i += kMergeThreads) {
+      const int rg = i / (4 * T), o = i - rg * 4 * T;
+      const int j0 = rg * n / kMergeChunks, j1 = (rg + 1) * n / kMergeChunks;
+      double sacc = 0.0;
+#pragma unroll 8
+      for (int j = j0; j < j1; ++j) sacc = fma(d.partials[(size_t)j * kPartStride(T) + 4 + o], fac[j], sacc);
+      part[i] = sacc;
+    }
+  __syncthreads();
   for (int i = tid; i < 4 * T; i += kMergeThreads) {
     const int t = i >> 2, ch = i & 3;
     double U;
     if (ok) {
-      double sacc = 0.0;
-#pragma unroll 8
-      for (int j = 0; j < n; ++j) sacc = fma(d.partials[(size_t)j * kPartStride(T) + 4 + i], fac[j], sacc);
+      double sacc = part[i];
+#pragma unroll
+      for (int rg = 1; rg < kMergeChunks; ++rg) sacc += part[rg * 4 * T + i];
       U = sacc / eta;
     } else {
       const int tt = t < d.U_len ? t : d.U_len - 1;
@@ -1530,7 +1544,7 @@ hipError_t launch_fused(const FusedBatch& b, int n_solves, const DeviceWeights& 
   }
   if (e != hipSuccess) return e;
   if (end && (e = hipEventRecord(end, s)) != hipSuccess) return e;
-  const size_t merge_lds = sizeof(double) * (3 * (kMergeThreads / 64) + (size_t)max_tiles);
+  const size_t merge_lds = sizeof(double) * (3 * (kMergeThreads / 64) + (size_t)kMergeChunks * 4 * max_T + (size_t)max_tiles);
   hipLaunchKernelGGL(k_fused_merge, dim3(n_solves), dim3(kMergeThreads), merge_lds, s, b);
   return hipGetLastError();
 }
