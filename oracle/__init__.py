@@ -20,9 +20,18 @@ Where the paper is silent the readings are listed in each module's
 docstring.  Every function works in float64 except where a precision
 contract (``precision.py``) rounds the SDF decoder's operands on purpose.
 
-Functions without an independent pin: the learned-SDF *behaviour* of the
-paper (no trained weights exist here; seeded random weights stand in), so
-results that depend on a trained decoder are "parity unpinned".
+Every function is pinned by tests/test_oracle_*.py against something other
+than itself (closed forms, hand values, library routines, invariants, brute
+force).  Not pinned: the learned-SDF *behaviour* of the paper (no trained
+weights exist here; seeded random weights stand in), so results that depend
+on a trained decoder are "parity unpinned".
+
+Reduced-precision bookkeeping (``precision.near_tie_mask``,
+``sdf.mlp_alternatives``, ``solve(..., near_ties=...)``): under the ``bf16``
+and ``fp8`` contracts an activation within a small window of a rounding
+boundary may legitimately round either way in a float32 evaluation; the
+oracle reports how many there are and the range of the field over every
+combination of those roundings.
 """
 from .philox import philox4x64_10, uniforms_from_words, box_muller, control_noise
 from .dynamics import rollout, rotor_rollout, quat_mul, thrust_axis

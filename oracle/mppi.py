@@ -33,7 +33,8 @@ import numpy as np
 from .dynamics import rollout, rotor_rollout
 from .philox import control_noise
 from .precision import contract_weights
-from .sdf import gate_sdf_analytic, mlp_concat
+from .precision import NEAR_TIE_ABS, NEAR_TIE_REL
+from .sdf import gate_sdf_analytic, mlp_alternatives, mlp_concat
 
 FLAG_SDF_AT_P0 = 1 << 1
 
@@ -50,13 +51,50 @@ def hover_sequence(T, mass, gravity, rotor=False):
     return U
 
 
+# A pivot of the Cholesky factorisation within PIVOT_TOL of the matrix scale
+# max |Sigma_ij| counts as zero (a semi-definite direction); the rest of its
+# column must then vanish to within OFFDIAG_TOL of the scale, else Sigma is
+# not positive semi-definite.
+PIVOT_TOL = 1e-12
+OFFDIAG_TOL = 1e-9
+
+
 def noise_factor(Sigma):
-    """Lower-triangular L with L L^T = Sigma; diagonal Sigma -> sqrt(diag),
-    which also admits zero variances."""
-    Sigma = np.asarray(Sigma, dtype=np.float64)
-    if np.count_nonzero(Sigma - np.diag(np.diag(Sigma))) == 0:
-        return np.diag(np.sqrt(np.diag(Sigma)))
-    return np.linalg.cholesky(Sigma)
+    """Lower-triangular L with L L^T = Sigma (Section IV-A: delta u ~ N(0,
+    Sigma), sampled as L n with n standard normal).
+
+    Diagonal Sigma -> sqrt(diag), which admits zero variances.  Otherwise the
+    column-by-column Cholesky factorisation: L_jj = sqrt(Sigma_jj - sum_k<j
+    L_jk^2), L_ij = (Sigma_ij - sum_k<j L_ik L_jk) / L_jj.  Reading for a
+    semi-definite Sigma (the factor is then not unique): a zero pivot leaves
+    its whole column zero, which is the factor of a positive definite Sigma
+    in the limit and keeps L L^T = Sigma.  Raises ValueError when Sigma is not
+    symmetric positive semi-definite."""
+    S = np.asarray(Sigma, dtype=np.float64).reshape(4, 4)
+    if not np.all(np.isfinite(S)):
+        raise ValueError("Sigma has non-finite entries")
+    scale = float(np.max(np.abs(S)))
+    if np.max(np.abs(S - S.T)) > 1e-12 * max(scale, 1.0):
+        raise ValueError("Sigma is not symmetric")
+    if np.count_nonzero(S - np.diag(np.diag(S))) == 0:
+        if np.any(np.diag(S) < 0):
+            raise ValueError("Sigma has a negative variance")
+        return np.diag(np.sqrt(np.diag(S)))
+    L = np.zeros((4, 4))
+    for j in range(4):
+        d = S[j, j] - sum(L[j, k] ** 2 for k in range(j))
+        if d < -PIVOT_TOL * scale:
+            raise ValueError("Sigma is not positive semi-definite")
+        zero_pivot = d <= PIVOT_TOL * scale
+        L[j, j] = 0.0 if zero_pivot else np.sqrt(d)
+        for i in range(j + 1, 4):
+            r = S[i, j] - sum(L[i, k] * L[j, k] for k in range(j))
+            if zero_pivot:
+                if abs(r) > OFFDIAG_TOL * scale:
+                    raise ValueError("Sigma is not positive semi-definite")
+            else:
+                L[i, j] = r / L[j, j]
+    return L
 
 
 def sample_controls(prob, model, U_nom):
@@ -71,14 +109,24 @@ def gate_frame_points(p_world, R, t):
     return (p_world - t) @ R
 
 
-def sdf_values(p_rel, prob, weights, contract, act_scales, sdf_kind):
-    """max over gates of the decoder at the query positions; shape (K, T)."""
+def sdf_values(p_rel, prob, weights, contract, act_scales, sdf_kind, ties=None):
+    """max over gates of the decoder at the query positions; shape (K, T).
+
+    ``ties`` (optional dict) receives (K, T) arrays under the ``bf16`` /
+    ``fp8`` contracts: "count", the near-tie activations of the position
+    summed over the gates, and "lo" / "hi", the range of the max over gates
+    when those roundings go either way (sdf.mlp_alternatives; the maximum of
+    per-gate ranges is the range of the maximum)."""
     K, T, G = prob["K"], prob["T"], prob["G"]
     sel = slice(0, T) if prob["flags"] & FLAG_SDF_AT_P0 else slice(1, T + 1)
     pts = (p_rel[:, sel, :] + prob["x0"][0:3]).reshape(-1, 3)
     best = np.full(pts.shape[0], -np.inf)
     if sdf_kind == "mlp":
         W, b = contract_weights(weights[0], weights[1], contract)
+    if ties is not None:
+        cnt = np.zeros(pts.shape[0], dtype=np.int64)
+        lo = np.full(pts.shape[0], -np.inf)
+        hi = np.full(pts.shape[0], -np.inf)
     for g in range(G):
         pg = gate_frame_points(pts, prob["gate_R"][g], prob["gate_t"][g])
         if sdf_kind == "analytic":
@@ -89,7 +137,17 @@ def sdf_values(p_rel, prob, weights, contract, act_scales, sdf_kind):
             step = 1 << 15
             for i in range(0, pg.shape[0], step):
                 s[i:i + step] = mlp_concat(pg[i:i + step], z, W, b, contract, act_scales)
+                if ties is not None:
+                    c, a, e = mlp_alternatives(pg[i:i + step], z, W, b, contract, act_scales,
+                                               ties.get("window", (NEAR_TIE_REL, NEAR_TIE_ABS)))
+                    cnt[i:i + step] += c
+                    lo[i:i + step] = np.maximum(lo[i:i + step], a)
+                    hi[i:i + step] = np.maximum(hi[i:i + step], e)
         best = np.maximum(best, s)
+    if ties is not None:
+        ties["count"] = cnt.reshape(K, T)
+        ties["lo"] = lo.reshape(K, T)
+        ties["hi"] = hi.reshape(K, T)
     return best.reshape(K, T)
 
 
@@ -140,7 +198,7 @@ def shift_warm_start(U):
 
 
 def solve(prob, weights, model, contract="fp32", sdf_kind="mlp", act_scales=None,
-          U_nom=None):
+          U_nom=None, near_ties=False):
     """One MPPI iteration.  ``weights`` = (W list, b list) float32 as given
     to the library; ``model`` = dict(mass, gravity, u_lo, u_hi), plus for the
     rotor-thrust-rate input (kind "rotor") inertia, arm_length, yaw_coeff,
@@ -148,7 +206,13 @@ def solve(prob, weights, model, contract="fp32", sdf_kind="mlp", act_scales=None
 
     Returns a dict with U_star (T, 4), u0 (4,), J (K,), w (K,), rho, log_eta,
     ess, status and the intermediates samples (K, T, 4), p_rel (K, T+1, 3),
-    sdf (K, T)."""
+    sdf (K, T).  With ``near_ties`` (``bf16`` / ``fp8`` contracts; True, or
+    a (relative, absolute) near-tie window) also near_tie (K, T): per query
+    position the number of activations feeding the hidden layers that lie
+    within the near-tie window of a rounding boundary
+    (precision.near_tie_mask), summed over the gates, and sdf_lo / sdf_hi
+    (K, T): the range of the field at that position over every legitimate
+    rounding of those activations (sdf.mlp_alternatives)."""
     T = prob["T"]
     if U_nom is None:
         U_nom = prob["U_nom"]
@@ -161,7 +225,12 @@ def solve(prob, weights, model, contract="fp32", sdf_kind="mlp", act_scales=None
         p_rel, q, _ = rotor_rollout(prob["x0"], prob["thrust0"], u, prob["dt"], model)
     else:
         p_rel, q, _ = rollout(prob["x0"], u, prob["dt"], model["mass"], model["gravity"])
-    s = sdf_values(p_rel, prob, weights, contract, act_scales, sdf_kind)
+    ties = None
+    if near_ties:
+        if contract not in ("bf16", "fp8") or sdf_kind != "mlp":
+            raise ValueError("near ties are counted for the MLP under the bf16 and fp8 contracts")
+        ties = {} if near_ties is True else {"window": tuple(near_ties)}
+    s = sdf_values(p_rel, prob, weights, contract, act_scales, sdf_kind, ties)
     J_gate = progress_cost_closed(p_rel, prob["x0"][0:3], prob["wp"])
     J_sdf = np.sum(np.maximum(0.0, prob["d_safe"] - s), axis=1)
     J_u = np.sum(u * u, axis=(1, 2))
@@ -176,4 +245,5 @@ def solve(prob, weights, model, contract="fp32", sdf_kind="mlp", act_scales=None
         "U_star": U_star, "u0": U_star[0].copy(), "U_next": shift_warm_start(U_star),
         "J": J, "w": w, "rho": rho, "log_eta": log_eta, "ess": ess,
         "samples": u, "p_rel": p_rel, "q": q, "sdf": s,
+        **({"near_tie": ties["count"], "sdf_lo": ties["lo"], "sdf_hi": ties["hi"]} if ties is not None else {}),
     }

@@ -27,7 +27,7 @@ from __future__ import annotations
 import numpy as np
 import torch
 
-from .precision import bf16_round, e4m3_round
+from .precision import NEAR_TIE_ABS, NEAR_TIE_REL, bf16_round, bf16_split2, e4m3_round, near_tie_mask
 
 C_HALF_WIDTH = 0.5
 TAN_ALPHA = 0.5
@@ -57,10 +57,20 @@ def _hidden_input(h, layer, contract, act_scales):
     """Operand of hidden layer ``layer`` (1-based H x H layer) under a contract."""
     if contract == "bf16":
         return _t(bf16_round(h.numpy()))
+    if contract == "bf16x2":
+        hi, lo = bf16_split2(h.numpy())
+        return _t(hi) + _t(lo)
     if contract == "fp8":
         s = act_scales[layer - 1]
         return _t(e4m3_round(h.numpy() / s) * s)
     return h
+
+
+def _grid_round(x, contract, scale):
+    """The contract's activation rounding (bf16, or E4M3 of x / scale)."""
+    if contract == "fp8":
+        return e4m3_round(x / scale) * scale
+    return bf16_round(x)
 
 
 def _mlp_tail(h, W, b, contract, act_scales):
@@ -70,6 +80,73 @@ def _mlp_tail(h, W, b, contract, act_scales):
         a = _hidden_input(h, l, contract, act_scales)
         h = _softplus_t(a @ _t(W[l]).T + _t(b[l]))
     return h @ _t(W[n - 1]).T + _t(b[n - 1])
+
+
+# Enumeration limit of the alternative roundings of one query row: at most
+# 2^MAX_TIE_BITS combinations per layer.
+MAX_TIE_BITS = 12
+
+
+def _alt_range(x, l, W, b, contract, act_scales, window):
+    """Range (min, max) of the decoder output over every legitimate rounding
+    of the activation row x (float64, the input of hidden layer l, 1-based)
+    and of the rows it leads to.  Elements within the near-tie window of a
+    rounding boundary may round either way (both candidates: the roundings
+    of x - w and x + w); each combination is carried through the next layer
+    exactly, whose own near ties are enumerated in turn."""
+    n = len(W)
+    sc = act_scales[l - 1] if contract == "fp8" else 1.0
+    rel, abs_ = window
+    w = rel * np.abs(x) + abs_
+    lo_c, hi_c = _grid_round(x - w, contract, sc), _grid_round(x + w, contract, sc)
+    idx = np.nonzero(lo_c != hi_c)[0]
+    if idx.size > MAX_TIE_BITS:
+        raise ValueError(f"{idx.size} near ties in one activation row: too many to enumerate")
+    base = _grid_round(x, contract, sc)
+    m = 1 << idx.size
+    A = np.broadcast_to(base, (m, x.size)).copy()
+    for j, i in enumerate(idx):
+        pick = ((np.arange(m) >> j) & 1).astype(bool)
+        A[pick, i] = hi_c[i]
+        A[~pick, i] = lo_c[i]
+    H = np.logaddexp(0.0, A @ np.asarray(W[l], dtype=np.float64).T + np.asarray(b[l], dtype=np.float64))
+    if l + 1 == n - 1:
+        s = H @ np.asarray(W[n - 1], dtype=np.float64)[0] + float(b[n - 1][0])
+        return float(s.min()), float(s.max())
+    lo, hi = np.inf, -np.inf
+    for r in range(m):
+        a, c = _alt_range(H[r], l + 1, W, b, contract, act_scales, window)
+        lo, hi = min(lo, a), max(hi, c)
+    return lo, hi
+
+
+def mlp_alternatives(pg, z, W, b, contract, act_scales=None, window=(NEAR_TIE_REL, NEAR_TIE_ABS)):
+    """Near ties of the decoder under the ``bf16`` / ``fp8`` contracts for
+    points pg (N, 3): per query row the number of activations feeding the
+    hidden layers that lie within the near-tie window of a rounding boundary
+    (precision.near_tie_mask), and the range [s_lo, s_hi] of the output over
+    every combination of their legitimate roundings, cascades into later
+    layers included (s_lo = s_hi = s for a row without near ties).
+    ``W``/``b`` as in mlp_concat (already under the contract)."""
+    if contract not in ("bf16", "fp8"):
+        raise ValueError(f"near ties are defined for the bf16 and fp8 contracts, not {contract!r}")
+    F = pe_freqs_of(W[0], z.shape[-1])
+    x = np.concatenate([positional_encoding(pg, F), np.broadcast_to(z, (pg.shape[0], z.shape[-1]))], axis=1)
+    h1 = _softplus_t(_t(x) @ _t(W[0]).T + _t(b[0])).numpy()
+    n = len(W)
+    count = np.zeros(pg.shape[0], dtype=np.int64)
+    # rows with a near tie in any hidden input: found along the contract's own pass
+    h = h1
+    for l in range(1, n - 1):
+        sc = act_scales[l - 1] if contract == "fp8" else 1.0
+        count += np.sum(near_tie_mask(h, contract, scale=sc, rel=window[0], abs_=window[1]), axis=1)
+        a = _hidden_input(_t(h), l, contract, act_scales)
+        h = _softplus_t(a @ _t(W[l]).T + _t(b[l])).numpy()
+    s = h @ np.asarray(W[n - 1], dtype=np.float64)[0] + float(b[n - 1][0])
+    s_lo, s_hi = s.copy(), s.copy()
+    for r in np.nonzero(count)[0]:
+        s_lo[r], s_hi[r] = _alt_range(h1[r], 1, W, b, contract, act_scales, window)
+    return count, s_lo, s_hi
 
 
 def pe_freqs_of(W0, latent_dim):
