@@ -116,7 +116,9 @@ def sdf_values(p_rel, prob, weights, contract, act_scales, sdf_kind, ties=None):
     ``fp8`` contracts: "count", the near-tie activations of the position
     summed over the gates, and "lo" / "hi", the range of the max over gates
     when those roundings go either way (sdf.mlp_alternatives; the maximum of
-    per-gate ranges is the range of the maximum)."""
+    per-gate ranges is the range of the maximum); and "alts", a dict flat
+    position index (k T + t) -> every distinct value of the max over gates
+    over those roundings, for the positions with near ties."""
     K, T, G = prob["K"], prob["T"], prob["G"]
     sel = slice(0, T) if prob["flags"] & FLAG_SDF_AT_P0 else slice(1, T + 1)
     pts = (p_rel[:, sel, :] + prob["x0"][0:3]).reshape(-1, 3)
@@ -127,6 +129,7 @@ def sdf_values(p_rel, prob, weights, contract, act_scales, sdf_kind, ties=None):
         cnt = np.zeros(pts.shape[0], dtype=np.int64)
         lo = np.full(pts.shape[0], -np.inf)
         hi = np.full(pts.shape[0], -np.inf)
+        per_gate, per_gate_alts = [], []
     for g in range(G):
         pg = gate_frame_points(pts, prob["gate_R"][g], prob["gate_t"][g])
         if sdf_kind == "analytic":
@@ -134,20 +137,34 @@ def sdf_values(p_rel, prob, weights, contract, act_scales, sdf_kind, ties=None):
         else:
             z = prob["gate_z"][g].astype(np.float64)
             s = np.empty(pg.shape[0])
+            galts = {}
             step = 1 << 15
             for i in range(0, pg.shape[0], step):
                 s[i:i + step] = mlp_concat(pg[i:i + step], z, W, b, contract, act_scales)
                 if ties is not None:
-                    c, a, e = mlp_alternatives(pg[i:i + step], z, W, b, contract, act_scales,
-                                               ties.get("window", (NEAR_TIE_REL, NEAR_TIE_ABS)))
+                    c, a, e, v = mlp_alternatives(pg[i:i + step], z, W, b, contract, act_scales,
+                                                  ties.get("window", (NEAR_TIE_REL, NEAR_TIE_ABS)), values=True)
                     cnt[i:i + step] += c
                     lo[i:i + step] = np.maximum(lo[i:i + step], a)
                     hi[i:i + step] = np.maximum(hi[i:i + step], e)
+                    galts.update({i + r: vv for r, vv in v.items()})
         best = np.maximum(best, s)
+        if ties is not None:
+            per_gate.append(s)
+            per_gate_alts.append(galts)
     if ties is not None:
+        # values of the max over gates: every combination of the gates' values
+        alts = {}
+        for q in np.nonzero(cnt)[0]:
+            acc = np.array([-np.inf])
+            for s_g, a_g in zip(per_gate, per_gate_alts):
+                v = a_g.get(int(q), np.array([s_g[q]]))
+                acc = np.unique(np.maximum.outer(acc, v).ravel())
+            alts[int(q)] = acc
         ties["count"] = cnt.reshape(K, T)
         ties["lo"] = lo.reshape(K, T)
         ties["hi"] = hi.reshape(K, T)
+        ties["alts"] = alts
     return best.reshape(K, T)
 
 
@@ -210,9 +227,11 @@ def solve(prob, weights, model, contract="fp32", sdf_kind="mlp", act_scales=None
     a (relative, absolute) near-tie window) also near_tie (K, T): per query
     position the number of activations feeding the hidden layers that lie
     within the near-tie window of a rounding boundary
-    (precision.near_tie_mask), summed over the gates, and sdf_lo / sdf_hi
+    (precision.near_tie_mask), summed over the gates, sdf_lo / sdf_hi
     (K, T): the range of the field at that position over every legitimate
-    rounding of those activations (sdf.mlp_alternatives)."""
+    rounding of those activations (sdf.mlp_alternatives), and sdf_alts: a
+    dict flat position (k T + t) -> every distinct field value over those
+    roundings, for the positions with near ties."""
     T = prob["T"]
     if U_nom is None:
         U_nom = prob["U_nom"]
@@ -231,6 +250,21 @@ def solve(prob, weights, model, contract="fp32", sdf_kind="mlp", act_scales=None
             raise ValueError("near ties are counted for the MLP under the bf16 and fp8 contracts")
         ties = {} if near_ties is True else {"window": tuple(near_ties)}
     s = sdf_values(p_rel, prob, weights, contract, act_scales, sdf_kind, ties)
+    out = costs_and_update(prob, u, p_rel, q, s, U_nom)
+    out.update({"samples": u, "p_rel": p_rel, "q": q, "sdf": s})
+    if ties is not None:
+        out.update({"near_tie": ties["count"], "sdf_lo": ties["lo"], "sdf_hi": ties["hi"],
+                    "sdf_alts": ties["alts"]})
+    return out
+
+
+def costs_and_update(prob, u, p_rel, q, s, U_nom):
+    """Costs (eqs. 5-9 with the control effort) of rollouts u (K, T, 4) with
+    positions p_rel, attitudes q and field values s (K, T) at their query
+    points, then the update (eq. mppi_update).  ``solve`` calls it with the
+    field it evaluated; under the ``bf16`` / ``fp8`` contracts a caller may
+    pass another of the legitimate fields (values from ``sdf_lo`` / ``sdf_hi``
+    at near-tie positions) to get the update that goes with that rounding."""
     J_gate = progress_cost_closed(p_rel, prob["x0"][0:3], prob["wp"])
     J_sdf = np.sum(np.maximum(0.0, prob["d_safe"] - s), axis=1)
     J_u = np.sum(u * u, axis=(1, 2))
@@ -239,11 +273,9 @@ def solve(prob, weights, model, contract="fp32", sdf_kind="mlp", act_scales=None
         J = J + prob["Q_vis"] * alignment_cost(p_rel, q, prob)
     U_star, w, rho, log_eta, ess, ok = mppi_update(J, u, prob["lam"])
     if not ok:
-        U_star = U_nom.copy()
+        U_star = np.asarray(U_nom, dtype=np.float64).copy()
     return {
         "status": STATUS_OK if ok else STATUS_ENUMERIC,
         "U_star": U_star, "u0": U_star[0].copy(), "U_next": shift_warm_start(U_star),
         "J": J, "w": w, "rho": rho, "log_eta": log_eta, "ess": ess,
-        "samples": u, "p_rel": p_rel, "q": q, "sdf": s,
-        **({"near_tie": ties["count"], "sdf_lo": ties["lo"], "sdf_hi": ties["hi"]} if ties is not None else {}),
     }

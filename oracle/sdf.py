@@ -83,17 +83,17 @@ def _mlp_tail(h, W, b, contract, act_scales):
 
 
 # Enumeration limit of the alternative roundings of one query row: at most
-# 2^MAX_TIE_BITS combinations per layer.
+# MAX_TIE_BITS tied elements per layer.
 MAX_TIE_BITS = 12
 
 
-def _alt_range(x, l, W, b, contract, act_scales, window):
-    """Range (min, max) of the decoder output over every legitimate rounding
-    of the activation row x (float64, the input of hidden layer l, 1-based)
-    and of the rows it leads to.  Elements within the near-tie window of a
-    rounding boundary may round either way (both candidates: the roundings
-    of x - w and x + w); each combination is carried through the next layer
-    exactly, whose own near ties are enumerated in turn."""
+def _alt_values(x, l, W, b, contract, act_scales, window):
+    """Every output value of the decoder over the legitimate roundings of the
+    activation row x (float64, the input of hidden layer l, 1-based) and of
+    the rows it leads to (sorted, distinct).  Elements within the near-tie
+    window of a rounding boundary may round either way (both candidates: the
+    roundings of x - w and x + w); each combination is carried through the
+    next layer exactly, whose own near ties are enumerated in turn."""
     n = len(W)
     sc = act_scales[l - 1] if contract == "fp8" else 1.0
     rel, abs_ = window
@@ -103,30 +103,32 @@ def _alt_range(x, l, W, b, contract, act_scales, window):
     if idx.size > MAX_TIE_BITS:
         raise ValueError(f"{idx.size} near ties in one activation row: too many to enumerate")
     base = _grid_round(x, contract, sc)
-    m = 1 << idx.size
+    # the candidates of a tied element: the roundings of x - w, x and x + w
+    # (x's own differs from both only when the window spans two boundaries)
+    cands = [np.unique([lo_c[i], base[i], hi_c[i]]) for i in idx]
+    m = int(np.prod([c.size for c in cands])) if cands else 1
     A = np.broadcast_to(base, (m, x.size)).copy()
-    for j, i in enumerate(idx):
-        pick = ((np.arange(m) >> j) & 1).astype(bool)
-        A[pick, i] = hi_c[i]
-        A[~pick, i] = lo_c[i]
+    rep = 1
+    for c, i in zip(cands, idx):
+        A[:, i] = c[(np.arange(m) // rep) % c.size]
+        rep *= c.size
     H = np.logaddexp(0.0, A @ np.asarray(W[l], dtype=np.float64).T + np.asarray(b[l], dtype=np.float64))
     if l + 1 == n - 1:
-        s = H @ np.asarray(W[n - 1], dtype=np.float64)[0] + float(b[n - 1][0])
-        return float(s.min()), float(s.max())
-    lo, hi = np.inf, -np.inf
-    for r in range(m):
-        a, c = _alt_range(H[r], l + 1, W, b, contract, act_scales, window)
-        lo, hi = min(lo, a), max(hi, c)
-    return lo, hi
+        return np.unique(H @ np.asarray(W[n - 1], dtype=np.float64)[0] + float(b[n - 1][0]))
+    return np.unique(np.concatenate([_alt_values(H[r], l + 1, W, b, contract, act_scales, window)
+                                     for r in range(m)]))
 
 
-def mlp_alternatives(pg, z, W, b, contract, act_scales=None, window=(NEAR_TIE_REL, NEAR_TIE_ABS)):
+def mlp_alternatives(pg, z, W, b, contract, act_scales=None, window=(NEAR_TIE_REL, NEAR_TIE_ABS),
+                     values=False):
     """Near ties of the decoder under the ``bf16`` / ``fp8`` contracts for
     points pg (N, 3): per query row the number of activations feeding the
     hidden layers that lie within the near-tie window of a rounding boundary
     (precision.near_tie_mask), and the range [s_lo, s_hi] of the output over
     every combination of their legitimate roundings, cascades into later
-    layers included (s_lo = s_hi = s for a row without near ties).
+    layers included (s_lo = s_hi = s for a row without near ties).  With
+    ``values`` also a dict row -> array of every distinct output value over
+    those roundings, for the rows with near ties.
     ``W``/``b`` as in mlp_concat (already under the contract)."""
     if contract not in ("bf16", "fp8"):
         raise ValueError(f"near ties are defined for the bf16 and fp8 contracts, not {contract!r}")
@@ -144,8 +146,14 @@ def mlp_alternatives(pg, z, W, b, contract, act_scales=None, window=(NEAR_TIE_RE
         h = _softplus_t(a @ _t(W[l]).T + _t(b[l])).numpy()
     s = h @ np.asarray(W[n - 1], dtype=np.float64)[0] + float(b[n - 1][0])
     s_lo, s_hi = s.copy(), s.copy()
+    vals = {}
     for r in np.nonzero(count)[0]:
-        s_lo[r], s_hi[r] = _alt_range(h1[r], 1, W, b, contract, act_scales, window)
+        v = _alt_values(h1[r], 1, W, b, contract, act_scales, window)
+        s_lo[r], s_hi[r] = v[0], v[-1]
+        if values:
+            vals[int(r)] = v
+    if values:
+        return count, s_lo, s_hi, vals
     return count, s_lo, s_hi
 
 

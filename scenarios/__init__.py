@@ -107,6 +107,22 @@ def yaw_rotation(psi):
     return np.array([[c, -s, 0.0], [s, c, 0.0], [0.0, 0.0, 1.0]])
 
 
+def correlated_sigma(seed, rank=4, sigma=(2.0, 0.5, 0.5, 0.3)):
+    """A full (non-diagonal) noise covariance with standard deviations
+    ``sigma`` and seeded random correlations: Sigma = D C D with C the
+    correlation matrix of B B^T, B a 4 x rank Gaussian matrix.  rank < 4
+    gives a singular positive semi-definite Sigma (some channel an exact
+    combination of the others)."""
+    rng = np.random.default_rng(seed)
+    B = rng.standard_normal((4, rank))
+    S = B @ B.T
+    dinv = 1.0 / np.sqrt(np.diag(S))
+    C = S * dinv[:, None] * dinv[None, :]
+    D = np.asarray(sigma, dtype=np.float64)
+    Sig = C * D[:, None] * D[None, :]
+    return 0.5 * (Sig + Sig.T)
+
+
 def _initial_state(rng, start):
     """State x0 = [p(3), q(w,x,y,z)(4), v(3), omega(3)]."""
     x0 = np.zeros(13)

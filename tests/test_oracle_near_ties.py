@@ -101,11 +101,14 @@ def _hand_decoder():
 def test_alternatives_hand_decoder():
     W, b, z = _hand_decoder()
     pg = np.zeros((1, 3))
-    count, lo, hi = mlp_alternatives(pg, z, W, b, "bf16")
+    count, lo, hi, vals = mlp_alternatives(pg, z, W, b, "bf16", values=True)
     sp = lambda v: math.log1p(math.exp(v))
     assert count.tolist() == [1]
     assert abs(lo[0] - (sp(1.0) + sp(0.75))) <= 1e-15
     assert abs(hi[0] - (sp(1.0 + 2.0 ** -7) + sp(0.75))) <= 1e-15
+    # exactly the two roundings of the tied activation
+    assert list(vals) == [0] and vals[0].size == 2
+    assert abs(vals[0][0] - lo[0]) <= 1e-15 and abs(vals[0][1] - hi[0]) <= 1e-15
     # the oracle's own rounding (ties to even: 1) is one end of the range
     assert abs(mlp_concat(pg, z, W, b, "bf16")[0] - lo[0]) <= 1e-15
 
@@ -139,13 +142,17 @@ def test_alternatives_contain_every_perturbed_evaluation(contract):
     pg = rng.uniform(-2, 2, (40, 3))
     z = rng.standard_normal(64)
     window = (2.0 ** -9, 2.0 ** -14)
-    count, lo, hi = mlp_alternatives(pg, z, W, b, contract, scales, window=window)
+    count, lo, hi, vals = mlp_alternatives(pg, z, W, b, contract, scales, window=window, values=True)
     assert np.count_nonzero(count) >= 20
     assert np.all(lo <= hi)
+    assert sorted(vals) == np.nonzero(count)[0].tolist()
     widen = 0
     for _ in range(64):
         s = _perturbed_eval(pg, z, W, b, contract, scales, window, rng)
         assert np.all(s >= lo - 1e-12) and np.all(s <= hi + 1e-12)
+        # every evaluation is one of the enumerated values of its row
+        for r, v in vals.items():
+            assert np.min(np.abs(v - s[r])) <= 1e-12
         widen += np.count_nonzero(np.abs(s - mlp_concat(pg, z, W, b, contract, scales)) > 1e-12)
     assert widen > 0      # the evaluators do take other roundings
 
@@ -158,6 +165,13 @@ def test_solve_reports_ranges_and_counts():
     assert np.all(r["sdf_lo"] <= r["sdf"] + 1e-15) and np.all(r["sdf"] <= r["sdf_hi"] + 1e-15)
     assert np.all(r["sdf_lo"][r["near_tie"] == 0] == r["sdf_hi"][r["near_tie"] == 0])
     assert np.any(r["sdf_lo"] < r["sdf_hi"])
+    # the value sets of the max over gates span exactly the reported ranges
+    # and hold the oracle's own value
+    assert sorted(r["sdf_alts"]) == np.flatnonzero(r["near_tie"]).tolist()
+    for q, v in r["sdf_alts"].items():
+        k, t = divmod(q, 8)
+        assert abs(v[0] - r["sdf_lo"][k, t]) <= 1e-13 and abs(v[-1] - r["sdf_hi"][k, t]) <= 1e-13
+        assert np.min(np.abs(v - r["sdf"][k, t])) <= 1e-13
     # zero window: no near ties, the range collapses to the contract's value
     r0 = solve(prob, (W, b), sc.MODEL, contract="bf16", near_ties=(0.0, 0.0))
     assert r0["near_tie"].sum() == 0 and np.allclose(r0["sdf_lo"], r0["sdf"], rtol=0, atol=1e-13)
