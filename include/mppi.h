@@ -103,7 +103,9 @@ typedef struct mppi_config {
   int32_t n_hidden;          /* hidden layers L >= 2: widths 67 -> H (L times) -> 1 */
   int32_t latent_dim;        /* must be 64 */
   int32_t K_max, T_max, G_max;  /* per-solve limits: K <= 16384, T <= 128, G <= 8 */
-  int32_t max_instances;     /* resident warm-start slots (instance table) */
+  int32_t max_instances;     /* resident warm-start slots (instance table); an instance keeps its slot
+                                for the engine's life, and a request for a new instance while the table is
+                                full fails with EAGAIN (the served path fails that ticket alone) */
   int32_t max_inflight;      /* solves on the device at once (served path) */
   int32_t queue_depth;       /* host queue capacity of mppi_submit */
   int32_t device;            /* HIP device ordinal */
@@ -123,6 +125,11 @@ typedef struct mppi_config {
   /* MPPI_DYN_ROTOR_RATES only (all > 0): principal inertia (kg m^2), arm
    * length (m), yaw drag torque per thrust (m), thrust and body-rate bounds */
   double inertia[3], arm_length, yaw_coeff, thrust_max, rate_max;
+  /* Served path: the most work one batch launch takes, in decoder query
+   * points (K T G summed over its solves); a batch always takes at least the
+   * oldest admissible request.  Bounds how long a request waits behind a
+   * burst.  0 = the default, 2^21 query points. */
+  uint64_t wave_queries_max;
 } mppi_config;
 
 /* Decoder weights, row-major float32 as a (n_out x n_in) matrix per layer
@@ -185,7 +192,8 @@ typedef struct mppi_result {
   double* costs;             /* optional K: total cost J_m */
   float* samples;            /* optional K x T x 4: clipped sampled controls (plain path only) */
   float* positions;          /* optional K x (T+1) x 3: positions relative to p_0 (plain path only) */
-  float* sdf;                /* optional K x T: max-over-gates field at the query points (plain path only) */
+  float* sdf;                /* optional K x T: max-over-gates field at the query points (plain and fused paths;
+                                mppi_step only) */
   double u0[4];              /* U*_0, the action to apply */
   double J_min;              /* min_m J_m */
   double log_eta;            /* log sum_m exp(-J_m / lambda) */
@@ -207,7 +215,9 @@ int mppi_create(const mppi_config* config, const mppi_sdf_weights* weights, mppi
  * Must not race other calls on the same engine. */
 int mppi_destroy(mppi_engine* engine);
 
-/* One blocking solve.  EINVAL: lambda <= 0 or non-finite, Sigma not PSD,
+/* One blocking solve.  Its device memory counts against the admission
+ * budget (EAGAIN while served solves hold the rest of it; ENOMEM if it can
+ * never fit).  EINVAL: lambda <= 0 or non-finite, Sigma not PSD,
  * K/T/G outside [1, max], non-finite x0 or U_nom, |q| not within 1e-6 of 1,
  * NULL U_star/gates, rotor thrusts outside [0, thrust_max].  ENUMERIC: every cost non-finite (U_star = nominal,
  * the resident warm start is kept).  Uses the engine's own stream. */
@@ -220,7 +230,9 @@ int mppi_submit(mppi_engine* engine, const mppi_request* request, uint64_t* tick
 
 /* MPPI_PENDING while the ticket's solve runs; otherwise copies the outcome
  * into *result (U_star etc. must be sized for that request), retires the
- * ticket and returns the solve's status.  ENOTFOUND: unknown/retired ticket. */
+ * ticket and returns the solve's status (EINVAL: an unobserved gate with no
+ * cached observation; EAGAIN: a new instance while the instance table was
+ * full).  ENOTFOUND: unknown/retired ticket. */
 int mppi_poll(mppi_engine* engine, uint64_t ticket, mppi_result* result);
 
 /* Block until every submitted solve has finished (results stay pollable). */
@@ -244,8 +256,9 @@ void mppi_reset_stats(mppi_engine* engine);
 /* Static description of a status code. */
 const char* mppi_status_str(int status);
 
-/* Device bytes one solve of this shape needs on this engine's path (the unit
- * of budget admission). */
+/* Device bytes one solve of this shape takes from the admission budget on
+ * this engine's path (its buffers plus, on the fused path, its share of a
+ * batch launch's descriptor block). */
 uint64_t mppi_solve_footprint(const mppi_engine* engine, int32_t K, int32_t T, int32_t G);
 
 /* Staged batches: n requests validated, packed and copied into device memory
@@ -255,7 +268,9 @@ uint64_t mppi_solve_footprint(const mppi_engine* engine, int32_t K, int32_t T, i
  * tick == MPPI_TICK_RESIDENT advance their resident warm start and tick on
  * the device at every launch.  Instance ids within a batch must be distinct
  * (EINVAL otherwise) and are held until mppi_batch_destroy (EAGAIN for other
- * calls on them meanwhile).  ENOMEM if the per-solve buffers do not fit.
+ * calls on them meanwhile).  The staged solves hold their memory against the
+ * admission budget until mppi_batch_destroy: ENOMEM if it can never fit,
+ * EAGAIN while served solves hold too much of it.
  * Launches are asynchronous on the engine's stream; mppi_batch_wait blocks
  * until they finish; mppi_batch_results copies the latest outcome of request
  * i into results[i] (caller-owned, U_star sized T_i x 4). */

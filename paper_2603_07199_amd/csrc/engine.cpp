@@ -173,6 +173,7 @@ struct mppi_batch {
   Staged st;
   hipEvent_t t0 = nullptr, t1 = nullptr, s0 = nullptr, s1 = nullptr;
   bool launched = false;
+  uint64_t reserved = 0;   // budget held until mppi_batch_destroy
 };
 
 namespace {
@@ -314,10 +315,25 @@ int tile_rollouts(const mppi_engine* e, int G) {
   return fused_tile_rollouts(e->cfg.precision, e->H, G);
 }
 
-SolveLayout layout_for(const mppi_engine* e, int K, int T, int G) {
+// exports: a blocking solve that returns its intermediates (plain path:
+// samples, positions and field values; fused path: field values).
+SolveLayout layout_for(const mppi_engine* e, int K, int T, int G, bool exports = false) {
   const int R = e->fused ? tile_rollouts(e, G) : 1;
   const int nt = e->fused ? (K + R - 1) / R : 0;
-  return solve_layout(K, T, G, e->H, e->fused, nt);
+  return solve_layout(K, T, G, e->H, e->fused, nt, e->fused && exports);
+}
+
+// Device bytes one solve takes from the budget: its block, plus on the fused
+// path its share of a batch's launch block (descriptor, tile list entries and
+// work counter), so that the launch block of any batch fits in the budget its
+// solves were admitted with.
+uint64_t admission_footprint(const mppi_engine* e, int K, int T, int G, bool exports = false) {
+  uint64_t fp = layout_for(e, K, T, G, exports).total;
+  if (e->fused) {
+    const int R = tile_rollouts(e, G);
+    fp += align_up(sizeof(SolveDesc)) + align_up(sizeof(int2) * (uint64_t)((K + R - 1) / R)) + kAlign;
+  }
+  return fp;
 }
 
 // Fill the upload part (descriptor + request data) of a solve whose device
@@ -455,6 +471,7 @@ void pack_solve(mppi_engine* e, const mppi_request* r, Solve* s, const double Lo
     d.wt = (double*)(base + lay.wt);
   } else {
     const int R = tile_rollouts(e, G);
+    d.sdf = s->exports ? (float*)(base + lay.sdf) : nullptr;
     d.partials = (double*)(base + lay.partials);
     d.tile_rollouts = R;
     d.n_tiles = (K + R - 1) / R;
@@ -518,12 +535,12 @@ int stage(mppi_engine* e, const std::vector<const mppi_request*>& reqs, bool wan
     s->flags = r->flags;
     s->want_w = want_w;
     s->want_J = want_J;
-    s->exports = exports && !e->fused;
+    s->exports = exports;
     if (rc == MPPI_OK) rc = acquire_slot(e, r->instance_id, &s->slot);
     if (rc == MPPI_OK && e->inst[s->slot].busy) rc = MPPI_EAGAIN;
     if (rc == MPPI_OK && !gates_cached_ok(e, r)) rc = MPPI_EINVAL;   // a gate never observed
     if (rc == MPPI_OK) {
-      s->lay = layout_for(e, r->K, r->T, r->G);
+      s->lay = layout_for(e, r->K, r->T, r->G, exports);
       if (!e->arena.alloc(s->lay.total, &s->off)) rc = MPPI_ENOMEM;
       else s->bytes = s->lay.total;
     }
@@ -625,12 +642,14 @@ int enqueue_fetch(mppi_engine* e, Solve* s, hipStream_t st) {
     HIPCHK(e, hipMemcpyAsync(s->J.data(), base + s->lay.J, sizeof(float) * K, hipMemcpyDeviceToHost, st));
   }
   if (s->exports) {
-    s->samples.resize((size_t)4 * T * K);
-    s->pos.resize((size_t)3 * (T + 1) * K);
+    if (!e->fused) {
+      s->samples.resize((size_t)4 * T * K);
+      s->pos.resize((size_t)3 * (T + 1) * K);
+      HIPCHK(e, hipMemcpyAsync(s->samples.data(), base + s->lay.samples, 4 * s->samples.size(),
+                               hipMemcpyDeviceToHost, st));
+      HIPCHK(e, hipMemcpyAsync(s->pos.data(), base + s->lay.pos, 4 * s->pos.size(), hipMemcpyDeviceToHost, st));
+    }
     s->sdf.resize((size_t)T * K);
-    HIPCHK(e, hipMemcpyAsync(s->samples.data(), base + s->lay.samples, 4 * s->samples.size(),
-                             hipMemcpyDeviceToHost, st));
-    HIPCHK(e, hipMemcpyAsync(s->pos.data(), base + s->lay.pos, 4 * s->pos.size(), hipMemcpyDeviceToHost, st));
     HIPCHK(e, hipMemcpyAsync(s->sdf.data(), base + s->lay.sdf, 4 * s->sdf.size(), hipMemcpyDeviceToHost, st));
   }
   return MPPI_OK;
@@ -650,20 +669,20 @@ void fill_result(const Solve* s, mppi_result* out) {
   if (out->weights && s->want_w && (int)s->wn.size() == K) memcpy(out->weights, s->wn.data(), sizeof(double) * K);
   if (out->costs && s->want_J && (int)s->J.size() == K)
     for (int k = 0; k < K; ++k) out->costs[k] = (double)s->J[k] + s->C0;
-  if (s->exports && !s->samples.empty()) {
+  if (s->exports) {
     const size_t TK = (size_t)T * K, T1K = (size_t)(T + 1) * K;
-    if (out->samples)
+    if (out->samples && !s->samples.empty())
       for (int k = 0; k < K; ++k)
         for (int t = 0; t < T; ++t)
           for (int c = 0; c < 4; ++c)
             out->samples[((size_t)k * T + t) * 4 + c] = s->samples[c * TK + (size_t)t * K + k];
-    if (out->positions)
+    if (out->positions && !s->pos.empty())
       for (int k = 0; k < K; ++k)
         for (int t = 0; t <= T; ++t)
           for (int c = 0; c < 3; ++c)
             out->positions[((size_t)k * (T + 1) + t) * 3 + c] =
                 (float)((double)s->pos[c * T1K + (size_t)t * K + k] + s->v0[c] * (t * s->dt));
-    if (out->sdf)
+    if (out->sdf && !s->sdf.empty())
       for (int k = 0; k < K; ++k)
         for (int t = 0; t < T; ++t) out->sdf[(size_t)k * T + t] = s->sdf[(size_t)t * K + k];
   }
@@ -972,6 +991,17 @@ int mppi_step(mppi_engine* e, const mppi_request* r, mppi_result* out) {
   const uint64_t t_submit = now_ns();
   Staged sg;
   const bool exports = out->samples || out->positions || out->sdf;
+  // the solve's memory counts against the budget the served path admits by
+  if (r->K < 1 || r->K > e->cfg.K_max || r->T < 1 || r->T > e->cfg.T_max || r->G < 1 || r->G > e->cfg.G_max)
+    return MPPI_EINVAL;
+  const uint64_t fp = admission_footprint(e, r->K, r->T, r->G, exports);
+  const int rr = e->adm->reserve(fp);
+  if (rr != 0) return rr == -2 ? MPPI_ENOMEM : MPPI_EAGAIN;
+  struct Unreserve {
+    Admission* a;
+    uint64_t b;
+    ~Unreserve() { a->unreserve(b); }
+  } unreserve{e->adm.get(), fp};
   int rc = stage(e, {r}, out->weights != nullptr, out->costs != nullptr, exports, 0, sg);
   if (rc != MPPI_OK) return rc;
   hipStream_t st = e->streams[0];
@@ -1010,9 +1040,9 @@ int mppi_submit(mppi_engine* e, const mppi_request* r, uint64_t* ticket) {
   std::lock_guard<std::mutex> lk(e->mu);
   int rc = validate(e, r, Lo);
   if (rc != MPPI_OK) return rc;
-  const uint64_t fp = layout_for(e, r->K, r->T, r->G).total;
+  const uint64_t fp = admission_footprint(e, r->K, r->T, r->G);
   const uint64_t t = e->next_ticket;
-  rc = e->adm->push(AdmissionItem{t, r->instance_id, fp});
+  rc = e->adm->push(AdmissionItem{t, r->instance_id, fp, (uint64_t)r->K * r->T * r->G});
   if (rc == -2) return MPPI_ENOMEM;
   if (rc == -3) return MPPI_EAGAIN;
   e->next_ticket++;
@@ -1067,7 +1097,7 @@ void mppi_reset_stats(mppi_engine* e) {
 
 uint64_t mppi_solve_footprint(const mppi_engine* e, int32_t K, int32_t T, int32_t G) {
   if (!e || K < 1 || T < 1 || G < 1) return 0;
-  return layout_for(e, K, T, G).total;
+  return admission_footprint(e, K, T, G);
 }
 
 int mppi_batch_create(mppi_engine* e, const mppi_request* reqs, int32_t n, mppi_batch** out) {
@@ -1077,16 +1107,32 @@ int mppi_batch_create(mppi_engine* e, const mppi_request* reqs, int32_t n, mppi_
   hipSetDevice(e->dev);
   auto b = std::make_unique<mppi_batch>();
   std::vector<const mppi_request*> rs;
-  for (int i = 0; i < n; ++i) rs.push_back(&reqs[i]);
+  uint64_t fp = 0;
+  for (int i = 0; i < n; ++i) {
+    rs.push_back(&reqs[i]);
+    const mppi_request& r = reqs[i];
+    if (r.K < 1 || r.K > e->cfg.K_max || r.T < 1 || r.T > e->cfg.T_max || r.G < 1 || r.G > e->cfg.G_max)
+      return MPPI_EINVAL;
+    fp += admission_footprint(e, r.K, r.T, r.G);
+  }
+  // the staged solves hold their memory against the served path's budget
+  const int rr = e->adm->reserve(fp);
+  if (rr != 0) return rr == -2 ? MPPI_ENOMEM : MPPI_EAGAIN;
+  b->reserved = fp;
   int rc = stage(e, rs, true, true, false, 0, b->st);
   if (rc == MPPI_OK && hipStreamSynchronize(e->streams[0]) != hipSuccess) {
     release_staged(e, b->st, true);
+    e->adm->unreserve(fp);
     return dev_fail(e, hipErrorUnknown);
   }
-  if (rc != MPPI_OK) return rc;
+  if (rc != MPPI_OK) {
+    e->adm->unreserve(fp);
+    return rc;
+  }
   for (hipEvent_t* ev : {&b->t0, &b->t1, &b->s0, &b->s1})
     if (hipEventCreate(ev) != hipSuccess) {
       release_staged(e, b->st, true);
+      e->adm->unreserve(fp);
       for (hipEvent_t x : {b->t0, b->t1, b->s0, b->s1})
         if (x) hipEventDestroy(x);
       return dev_fail(e, hipErrorOutOfMemory);
@@ -1157,6 +1203,7 @@ int mppi_batch_destroy(mppi_engine* e, mppi_batch* b) {
   std::lock_guard<std::mutex> lk(e->mu);
   hipStreamSynchronize(e->streams[0]);
   release_staged(e, b->st, true);
+  e->adm->unreserve(b->reserved);
   for (hipEvent_t ev : {b->t0, b->t1, b->s0, b->s1})
     if (ev) hipEventDestroy(ev);
   delete b;
@@ -1205,15 +1252,26 @@ void scheduler_loop(mppi_engine* e) {
     if (e->stop && e->inflight.empty()) break;
     bool launched = false;
     if (!e->stop && !e->sticky.load() && (int)e->inflight.size() < nstreams) {
+      const uint64_t cap = e->cfg.wave_queries_max ? e->cfg.wave_queries_max : (1ull << 21);
       auto adm = e->adm->admit([&](uint64_t id) {
         auto it = e->inst_map.find(id);
         return it != e->inst_map.end() && e->inst[it->second].busy;
-      });
-      // a request whose unobserved gate has no cached observation fails on
-      // its own instead of failing the wave it was admitted with
+      }, cap);
+      // a request that cannot run fails on its own instead of failing the
+      // batch it was admitted with: an unobserved gate without a cached
+      // observation (EINVAL), or a new instance when the instance table is
+      // full (EAGAIN; existing instances in the same batch still run)
+      int new_slots = 0;
       for (size_t i = 0; i < adm.size();) {
         const mppi_request* r = &e->pending[adm[i].ticket].req;
-        if (gates_cached_ok(e, r)) {
+        int fail = MPPI_OK;
+        if (!gates_cached_ok(e, r)) {
+          fail = MPPI_EINVAL;
+        } else if (!e->inst_map.count(r->instance_id)) {
+          if ((int)e->inst.size() + new_slots >= e->cfg.max_instances) fail = MPPI_EAGAIN;
+          else ++new_slots;
+        }
+        if (fail == MPPI_OK) {
           ++i;
           continue;
         }
@@ -1221,7 +1279,7 @@ void scheduler_loop(mppi_engine* e) {
         s->ticket = adm[i].ticket;
         s->T = r->T;
         s->res.assign(4 * s->T + RES_SCALARS, 0.0);
-        s->res[4 * s->T + RES_STATUS] = MPPI_EINVAL;
+        s->res[4 * s->T + RES_STATUS] = fail;
         s->want_w = s->want_J = false;
         s->t_submit = e->ticket_submit_ns[adm[i].ticket];
         s->t_done = now_ns();

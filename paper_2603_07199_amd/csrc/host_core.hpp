@@ -80,7 +80,8 @@ struct SolveLayout {
   uint64_t upload_bytes, total;
 };
 
-inline SolveLayout solve_layout(int K, int T, int G, int H, bool fused, int n_tiles) {
+// fused_sdf: a fused solve that exports its field values ([T][K] floats).
+inline SolveLayout solve_layout(int K, int T, int G, int H, bool fused, int n_tiles, bool fused_sdf = false) {
   SolveLayout L{};
   uint64_t o = 0;
   auto take = [&](uint64_t bytes) { const uint64_t r = o; o = align_up(o + bytes); return r; };
@@ -103,6 +104,7 @@ inline SolveLayout solve_layout(int K, int T, int G, int H, bool fused, int n_ti
     L.wt = take(8ull * K);
   } else {
     L.partials = take(8ull * (4 + 4 * T) * n_tiles);
+    if (fused_sdf) L.sdf = take(4ull * T * K);
   }
   L.total = o;
   return L;
@@ -112,10 +114,16 @@ inline SolveLayout solve_layout(int K, int T, int G, int H, bool fused, int n_ti
 // fits the free budget and an in-flight slot is free; requests never overtake
 // the head (no starvation of large requests), except that a head blocked only
 // by its instance being busy lets later requests of other instances pass.
+// One admit() pass forms one batch; it stops once the batch holds max_work
+// units of work (the first item is always taken), so that no launch grows
+// without bound under a burst and a request waits for at most one bounded
+// batch per stream.  Memory taken outside the queue (blocking solves, staged
+// batches) is counted against the same budget through reserve().
 struct AdmissionItem {
   uint64_t ticket;
   uint64_t instance_id;
   uint64_t footprint;
+  uint64_t work = 0;
 };
 
 class Admission {
@@ -129,10 +137,13 @@ class Admission {
     q_.push_back(it);
     return 0;
   }
-  // Pops every item admissible now, in FIFO order, given the busy instances.
+  // Pops the items admissible now, in FIFO order, given the busy instances,
+  // up to max_work units of work in total (0: no limit; the first item is
+  // taken whatever its work).
   template <class BusyFn>
-  std::vector<AdmissionItem> admit(BusyFn instance_busy) {
+  std::vector<AdmissionItem> admit(BusyFn instance_busy, uint64_t max_work = 0) {
     std::vector<AdmissionItem> out;
+    uint64_t work = 0;
     auto taken = [&](uint64_t id) {
       for (auto& o : out) if (o.instance_id == id) return true;
       return false;
@@ -141,13 +152,24 @@ class Admission {
       if (inflight_ >= max_inflight_) break;
       if (instance_busy(it->instance_id) || taken(it->instance_id)) { ++it; continue; }
       if (in_use_ + it->footprint > budget_) break;
+      if (max_work && !out.empty() && work + it->work > max_work) break;
       in_use_ += it->footprint;
+      work += it->work;
       ++inflight_;
       out.push_back(*it);
       it = q_.erase(it);
     }
     return out;
   }
+  // Budget for memory held outside the queue: 0 = taken, -2 = can never fit,
+  // -3 = does not fit now.
+  int reserve(uint64_t bytes) {
+    if (bytes > budget_) return -2;
+    if (in_use_ + bytes > budget_) return -3;
+    in_use_ += bytes;
+    return 0;
+  }
+  void unreserve(uint64_t bytes) { in_use_ -= bytes; }
   void complete(uint64_t footprint) {
     in_use_ -= footprint;
     --inflight_;

@@ -28,7 +28,7 @@
 //                   of two register accumulator sets, and the activation
 //                   epilogue (softplus, bf16 split / output dot) of block
 //                   s-3-2l from the other set
-//   wave 2          output sum, max over gates and hinge of block s-2-2L
+//   wave 2          output sum and max over gates of block s-2-2L
 //                   (L hidden H x H layers)
 // with one workgroup barrier per step.  A wave's products and its epilogue
 // work on different blocks, so the matrix cores and the vector units overlap
@@ -142,7 +142,7 @@ __host__ __device__ constexpr int pe_row_halves(int k32) { return 32 * k32 + 8; 
 __host__ __device__ constexpr size_t pe_slot_bytes(int k32) { return (size_t)2 * kRows * pe_row_halves(k32) * 2; }
 
 struct FusedLds {
-  size_t act, w1p, hb, wo, cf, rt, base, los, dp, hinge, pts, opart, jl, wt, fac, misc, xch, rot, feat, total;
+  size_t act, w1p, hb, wo, cf, rt, base, los, dp, field, pts, opart, jl, wt, fac, misc, xch, rot, feat, total;
 };
 
 // The activation buffers (input of hidden layer l, block parity p) share
@@ -173,7 +173,7 @@ __host__ __device__ FusedLds fused_lds(int Tm, int Gm, int max_tiles, int feat_k
   L.base = take(sizeof(float) * 3 * Gm * (Tm + 1));
   L.los = take(sizeof(float) * 2 * Tm);
   L.dp = take(sizeof(float) * 3 * kTileR * (Tm + 1));
-  L.hinge = take(sizeof(float) * kTileR * Tm);
+  L.field = take(sizeof(float) * kTileR * Tm);
   L.fac = take(sizeof(double) * max_tiles);
   // positional encoding: three slots of the FP16 feature table
   L.feat = take(pe_slot_bytes(feat_ks) * 3);
@@ -194,7 +194,7 @@ __host__ __device__ constexpr size_t frag_index(int l, int nb, int ks, int lane)
 struct Views {
   char *act, *xch;
   float* rot;      // rotor-thrust-rate input: thrusts (4) and body rate (3) per rollout
-  float *samp, *w1p, *hb, *wo, *cf, *rt, *base, *los, *dp, *hinge, *pts, *opart, *jl;
+  float *samp, *w1p, *hb, *wo, *cf, *rt, *base, *los, *dp, *field, *pts, *opart, *jl;
   char* feat;      // encoded-point features of three blocks (positional encoding only)
   double *wt, *fac;
   int* misc;
@@ -214,7 +214,7 @@ __device__ __forceinline__ Views make_views(char* lds, int Tm, int Gm, int max_t
   v.base = (float*)(lds + L.base);
   v.los = (float*)(lds + L.los);
   v.dp = (float*)(lds + L.dp);
-  v.hinge = (float*)(lds + L.hinge);
+  v.field = (float*)(lds + L.field);
   v.pts = (float*)(lds + L.pts);
   v.opart = (float*)(lds + L.opart);
   v.jl = (float*)(lds + L.jl);
@@ -339,7 +339,7 @@ __device__ __forceinline__ f32x4 mfma_lp(const FragT<P>& a, const FragT<P>& b, c
 // gate g of the block.
 struct EdgeConsts {
   int G, T, Pc, qoff, npos, p, g;
-  float invT, dsafe, bout;
+  float invT, bout;
 };
 
 __device__ __forceinline__ EdgeConsts edge_consts(const SolveDesc& d, int lane, int npos, float bout) {
@@ -352,7 +352,6 @@ __device__ __forceinline__ EdgeConsts edge_consts(const SolveDesc& d, int lane, 
   e.p = lane / e.G;
   e.g = lane - e.p * e.G;
   e.invT = 1.0f / (float)e.T;
-  e.dsafe = d.d_safe;
   e.bout = bout;
   return e;
 }
@@ -432,7 +431,8 @@ __device__ __forceinline__ void pe_block(const Views& V, const EdgeConsts& e, in
 
 // Output of this lane's row of block c (lanes 0 .. kRows-1 of one wave): sum
 // of the per-lane partials of the last layer's owners, max over each
-// position's gates, hinge into the tile's table.
+// position's gates into the tile's field table (the hinge is taken in the
+// tile epilogue).
 template <int WPL>
 __device__ __forceinline__ void chunk_reduce(const Views& V, const EdgeConsts& e, const float* opart, int c, int row) {
   float acc = 0.0f;
@@ -449,7 +449,7 @@ __device__ __forceinline__ void chunk_reduce(const Views& V, const EdgeConsts& e
     if (base + g < kRows) best = fmaxf(best, o);
   }
   const int q = c * e.Pc + e.p;
-  if (e.g == 0 && e.p < e.Pc && q < e.npos) V.hinge[q] = fmaxf(0.0f, e.dsafe - best);
+  if (e.g == 0 && e.p < e.Pc && q < e.npos) V.field[q] = best;
 }
 
 // Clipped control samples of the tile (Section IV-A) into V.samp.
@@ -555,12 +555,17 @@ __device__ void tile_epilogue(const Views& V, const SolveDesc& d, int k0, int Re
   // the decoder reused the samples' space: draw them again (same counters)
   tile_noise(V, d, k0, Re, tick);
   {
-    // hinge sum of rollout k over its T steps: blockDim / 16 (16 or 32)
-    // lanes per rollout, fixed butterfly
+    // hinge (eq. 7) summed over rollout k's T steps (eq. 8): blockDim / 16
+    // (16 or 32) lanes per rollout, fixed butterfly; the field values go out
+    // too when the solve asked for them
     const int lpr = blockDim.x / kTileR;
     const int k = tid / lpr, part = tid - k * lpr;
     float hs = 0.0f;
-    for (int t = part; t < T; t += lpr) hs += V.hinge[k * T + t];
+    for (int t = part; t < T; t += lpr) {
+      const float sv = V.field[k * T + t];
+      hs += fmaxf(0.0f, d.d_safe - sv);
+      if (d.sdf && k < Re) d.sdf[(size_t)t * d.K + k0 + k] = sv;
+    }
     for (int m = lpr / 2; m >= 1; m >>= 1) hs += __shfl_xor(hs, m, 64);
     if (part == 0 && k < Re) {
       const float J = V.jl[k] + d.Q_sdf * hs;
@@ -1137,7 +1142,7 @@ __host__ __device__ FusedLds wide_lds(int Tm, int Gm, int max_tiles) {
   L.base = take(sizeof(float) * 3 * Gm * (Tm + 1));
   L.los = take(sizeof(float) * 2 * Tm);
   L.dp = take(sizeof(float) * 3 * kTileR * (Tm + 1));
-  L.hinge = take(sizeof(float) * kTileR * Tm);
+  L.field = take(sizeof(float) * kTileR * Tm);
   L.fac = take(sizeof(double) * max_tiles);
   L.total = o;
   return L;
@@ -1159,7 +1164,7 @@ __device__ __forceinline__ Views make_wide_views(char* lds, int Tm, int Gm, int 
   v.base = (float*)(lds + L.base);
   v.los = (float*)(lds + L.los);
   v.dp = (float*)(lds + L.dp);
-  v.hinge = (float*)(lds + L.hinge);
+  v.field = (float*)(lds + L.field);
   v.jl = (float*)(lds + L.jl);
   v.wt = (double*)(lds + L.wt);
   v.fac = (double*)(lds + L.fac);
@@ -1337,7 +1342,7 @@ __device__ __forceinline__ void wide_output_part(const Views& V, const f32x4 (&a
 }
 
 // Output of row block c from the pair's two partials: max over each
-// position's gates, hinge into the tile's table (lanes 0 .. 15).
+// position's gates into the tile's field table (lanes 0 .. 15).
 __device__ __forceinline__ void wide_output_rows(const Views& V, const EdgeConsts& e, const float* op_in, int c,
                                                  int lane) {
   const int row = lane & (kRows - 1);
@@ -1349,7 +1354,7 @@ __device__ __forceinline__ void wide_output_rows(const Views& V, const EdgeConst
     if (base + g < kRows) best = fmaxf(best, o);
   }
   const int q = c * e.Pc + e.p;
-  if (lane < kRows && e.g == 0 && e.p < e.Pc && q < e.npos) V.hinge[q] = fmaxf(0.0f, e.dsafe - best);
+  if (lane < kRows && e.g == 0 && e.p < e.Pc && q < e.npos) V.field[q] = best;
 }
 
 template <int P, int H, int NHH, bool VFIRST>

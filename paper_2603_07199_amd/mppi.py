@@ -47,6 +47,7 @@ class mppi_config(C.Structure):
         ("dynamics", C.c_int32), ("pe_freqs", C.c_int32),
         ("inertia", C.c_double * 3), ("arm_length", C.c_double), ("yaw_coeff", C.c_double),
         ("thrust_max", C.c_double), ("rate_max", C.c_double),
+        ("wave_queries_max", C.c_uint64),
     ]
 
 
@@ -341,7 +342,7 @@ class Batch:
 def default_config(model, K_max=8192, T_max=64, G_max=8, hidden=256, n_hidden=3,
                    precision="fp32", path="plain", sdf_kind="mlp", max_instances=4096,
                    max_inflight=64, queue_depth=4096, budget=1 << 30, seed=0, timing=False,
-                   stream=None, device_pool=None, device_pool_bytes=0, pe_freqs=0):
+                   stream=None, device_pool=None, device_pool_bytes=0, pe_freqs=0, wave_queries_max=0):
     return {
         "precision": PREC[precision], "path": PATH[path], "sdf_kind": SDF[sdf_kind],
         "hidden": hidden, "n_hidden": n_hidden, "latent_dim": 64,
@@ -359,6 +360,7 @@ def default_config(model, K_max=8192, T_max=64, G_max=8, hidden=256, n_hidden=3,
         "inertia": list(model.get("inertia", (0.0, 0.0, 0.0))),
         "arm_length": float(model.get("arm_length", 0.0)), "yaw_coeff": float(model.get("yaw_coeff", 0.0)),
         "thrust_max": float(model.get("thrust_max", 0.0)), "rate_max": float(model.get("rate_max", 0.0)),
+        "wave_queries_max": int(wave_queries_max),
     }
 
 

@@ -166,12 +166,32 @@ int main() {
   assert(q2.in_use() == 0 && q2.inflight() == 0 && q2.queued() == 3);
   adm = q2.admit(none);
   assert(adm.size() == 2 && adm[0].ticket == 7 && adm[1].ticket == 9);
+  // work cap per batch: stops before the item that would pass it; the first
+  // item is taken whatever its work
+  Admission q3(1 << 20, 16, 16);
+  q3.push({20, 1, 10, 500}); q3.push({21, 2, 10, 400}); q3.push({22, 3, 10, 300}); q3.push({23, 4, 10, 5000});
+  adm = q3.admit(none, 1000);
+  assert(adm.size() == 2 && adm[0].ticket == 20 && adm[1].ticket == 21);
+  adm = q3.admit(none, 1000);
+  assert(adm.size() == 1 && adm[0].ticket == 22);
+  adm = q3.admit(none, 1000);
+  assert(adm.size() == 1 && adm[0].ticket == 23);
+  // memory reserved outside the queue counts against the same budget
+  Admission q4(1000, 4, 4);
+  assert(q4.reserve(1001) == -2 && q4.reserve(600) == 0 && q4.reserve(500) == -3);
+  q4.push({30, 1, 500, 1});
+  assert(q4.admit(none).empty());
+  q4.unreserve(600);
+  adm = q4.admit(none);
+  assert(adm.size() == 1 && q4.in_use() == 500);
   // layout: regions are disjoint, aligned, and grow with K, T, G
   SolveLayout L = solve_layout(4096, 50, 4, 256, false, 0);
   assert(L.total % kAlign == 0 && L.upload_bytes <= L.result);
   assert(L.samples >= L.result && L.total >= L.samples + 4ull * 4 * 50 * 4096);
   SolveLayout F = solve_layout(4096, 50, 4, 256, true, 256);
   assert(F.total < L.total);
+  SolveLayout FS = solve_layout(4096, 50, 4, 256, true, 256, true);   // fused with the field export
+  assert(FS.sdf >= F.partials && FS.total >= FS.sdf + 4ull * 50 * 4096 && FS.total > F.total);
   std::printf("HOST OK\n");
   return 0;
 }

@@ -3,35 +3,89 @@ matching precision contract (the oracle rounds exactly what the kernel's
 matrix cores consume):
 
 * BF16X3 (bfloat16 weights, activations split into three bfloat16 terms)
-  against ``bf16w``: residual activation error ~2^-24 relative, float32 level,
-  so u*_0 is gated at the float32 tolerance 1e-4;
+  against ``bf16w``: residual activation error ~2^-24 relative, float32 level;
 * F16X2 (the bfloat16-rounded weights held exactly in FP16 under a
   power-of-two scale, activations split into two FP16 terms) against
-  ``bf16w``: residual ~2^-22 relative, gated like BF16X3;
-* BF16X2 (two terms) against ``bf16w``: residual ~2^-16 relative; a float32
-  emulation of its arithmetic gives u*_0 errors up to 3.6e-4 on P1, so it is
-  gated at 1e-3 and reported;
-* BF16 against ``bf16`` and FP8 against ``fp8``: activations rounded to 8 / 4
-  significant bits flip where the float32 and float64 values straddle a
-  rounding boundary; each flip moves a cost by a discrete step that the
-  softmax (lambda = 1) can amplify, so the worst scenario is reported and the
-  gate is on the median u*_0 error and on the bulk of the per-rollout costs.
+  ``bf16w``: residual ~2^-22 relative;
+* BF16X2 (two bfloat16 terms, 16 significant bits) against ``bf16x2``, the
+  contract that drops the same bits: the two sides differ only where the
+  float32 and float64 activations put the low term on different sides of a
+  rounding boundary, by one unit of the low term (~2^-16 relative);
+  all three gated at the float32 tolerance 1e-4 on u*_0, with the per-query
+  field values compared element by element;
+* BF16 against ``bf16`` and FP8 against ``fp8``: an activation within the
+  float32-vs-float64 error of a rounding boundary may legitimately round
+  either way (a near tie), and each such flip moves the field by a discrete
+  step that the weights can amplify.  The oracle enumerates the field values
+  of every legitimate rounding; the device's field must be one of them at
+  every query, and u*_0 is gated against the oracle's update for the
+  device's own choice of roundings (the flip count is printed): BF16 at
+  1e-4.  The FP8 matrix-core products carry about 8 times the float32-level
+  error of the bfloat16 ones (measured: continuous field error up to 6e-6
+  against 7e-7), so the FP8 near-tie window is 8 times wider, at most 1 in
+  1,000 field values may still miss every enumerated rounding, and its
+  u*_0 is reported with a median gate of 1e-4 and a maximum of 5e-4.
 """
 import numpy as np
 import pytest
 
 import oracle
 import scenarios as sc
-from gpu_common import SIGMA_FLOOR, U0_TOL, require_gpu, say, u0_error
+from gpu_common import SIGMA_FLOOR, U0_TOL, adjudicate, require_gpu, say, u0_error
 from oracle.mppi import sample_controls
 from oracle.sdf import hidden_input_amax
 
 pytestmark = pytest.mark.gpu
 
-CONTRACT = {"bf16x2": "bf16w", "bf16x3": "bf16w", "f16x2": "bf16w", "bf16": "bf16", "fp8": "fp8"}
-U0_GATE = {"bf16x2": 1e-3, "bf16x3": U0_TOL, "f16x2": U0_TOL, "bf16": 2e-2}
-FP32_LEVEL = ("bf16x3", "f16x2")   # gated at the float32 tolerance
-U0_MEDIAN_GATE = {"fp8": 2e-3}
+CONTRACT = {"bf16x2": "bf16x2", "bf16x3": "bf16w", "f16x2": "bf16w", "bf16": "bf16", "fp8": "fp8"}
+FP32_LEVEL = ("bf16x3", "f16x2")   # float32-level agreement with bf16w
+ROUNDED = ("bf16", "fp8")          # activations rounded: near ties adjudicated
+# near-tie window (relative, absolute) per rounded kind: the oracle's default
+# for bfloat16, 8 times wider for FP8 (its products' larger error)
+WINDOW = {"bf16": True, "fp8": (2.0 ** -17, 2.0 ** -19)}
+# field values: float32 decoder arithmetic, |ds| <= 2e-5 (1 + |s|)
+SDF_TOL = 2e-5
+
+
+def _field_tol(ref_sdf):
+    return SDF_TOL * (1.0 + np.abs(ref_sdf))
+
+
+def _check_field(name, got, want):
+    d = np.abs(np.asarray(got, dtype=np.float64) - want)
+    bad = ~(d <= _field_tol(want))
+    assert not bad.any(), f"{name}: {int(bad.sum())} of {d.size} field values out of tolerance, max {d.max():.2e}"
+    return float(d.max())
+
+
+def _gate(precision, prob, out, ref, label, jtol=2e-5):
+    """The variant's parity gate: (u*_0 error, note).  Continuous contracts:
+    field element by element, costs, u*_0.  Rounded contracts: every field
+    value legitimate, then costs and u*_0 against the oracle's update for the
+    device's roundings."""
+    scale = np.abs(ref["J"]) + prob["Q_sdf"] * prob["T"] + 1.0
+    if precision in ROUNDED:
+        adj, info = adjudicate(prob, ref, out["sdf"], _field_tol(ref["sdf"]))
+        note = (f"near-tie positions {info['ties']}, flipped {info['flipped']}, max |ds| {info['worst']:.1e} "
+                f"({info['noisy']} above tol/4); vs oracle's own rounding {u0_error(out['u0'], ref['u0']):.2e}")
+        # FP8: a rare activation whose product error still exceeds the wide
+        # window may flip (seen: 1 of 9,216 positions); at most 1 in 1,000
+        limit = 0 if precision == "bf16" else max(1, out["sdf"].size // 1000)
+        assert info["bad"] <= limit, f"{label}: {info['bad']} field values match no legitimate rounding; {note}"
+        dJ = np.abs(out["J"] - adj["J"])
+        assert np.all(dJ <= jtol * scale), (dJ / scale).max()
+        return u0_error(out["u0"], adj["u0"]), note
+    ds = _check_field(label, out["sdf"], ref["sdf"])
+    dJ = np.abs(out["J"] - ref["J"])
+    assert np.all(dJ <= jtol * scale), (dJ / scale).max()
+    return u0_error(out["u0"], ref["u0"]), f"max |ds| {ds:.1e}"
+
+
+def _gate_u0(precision, errs):
+    if precision == "fp8":
+        assert np.median(errs) <= U0_TOL and max(errs) <= 5e-4
+    else:
+        assert max(errs) <= U0_TOL
 
 
 def _act_scales(layers, W, b, probs):
@@ -67,29 +121,23 @@ def test_p1_fused_precision_variants(precision):
         scales = _act_scales(layers, W, b, [sc.config_problem("P1", 0, K=256)])
     eng, w = _engine(M, layers, precision, 256, 20, 1, act_scale=scales)
     for d_safe in (0.3, 1.0):
-        errs, errs32, jrel = [], [], []
+        errs, errs32, notes = [], [], []
         for seed in range(1, 9):
             prob = sc.config_problem("P1", seed, d_safe=d_safe, instance_id=int(d_safe * 10) * 100 + seed)
-            ref = oracle.solve(prob, w, sc.MODEL, contract=CONTRACT[precision], act_scales=scales)
+            ref = oracle.solve(prob, w, sc.MODEL, contract=CONTRACT[precision], act_scales=scales,
+                               near_ties=WINDOW.get(precision, False))
             ref32 = oracle.solve(prob, w, sc.MODEL, contract="fp32")
-            out = eng.step(prob)
+            out = eng.step(prob, exports=True)
             assert out["rc"] == 0, out["rc"]
             assert abs(out["w"].sum() - 1.0) < 1e-12
-            errs.append(u0_error(out["u0"], ref["u0"]))
+            e, note = _gate(precision, prob, out, ref, f"P1 {precision} seed {seed}")
+            errs.append(e)
+            notes.append(note)
             errs32.append(u0_error(out["u0"], ref32["u0"]))
-            dJ = np.abs(out["J"] - ref["J"])
-            jrel.append(dJ / (np.abs(ref["J"]) + prob["Q_sdf"] * prob["T"] + 1.0))
-            if precision in FP32_LEVEL:
-                assert np.all(dJ <= 2e-5 * (np.abs(ref["J"]) + prob["Q_sdf"] * prob["T"] + 1.0)), dJ.max()
-        jr = np.concatenate(jrel)
+        worst = int(np.argmax(errs))
         say(f"P1 fused {precision} d_safe={d_safe}: u0 err vs {CONTRACT[precision]} max {max(errs):.2e} "
-            f"median {np.median(errs):.2e}; vs fp32 max {max(errs32):.2e}; relative cost error "
-            f"p50 {np.percentile(jr, 50):.1e} p99 {np.percentile(jr, 99):.1e} max {jr.max():.1e}")
-        if precision in U0_GATE:
-            assert max(errs) <= U0_GATE[precision]
-        else:
-            assert np.median(errs) <= U0_MEDIAN_GATE[precision]
-            assert np.percentile(jr, 90) <= 1e-3
+            f"median {np.median(errs):.2e} (worst: {notes[worst]}); vs fp32 max {max(errs32):.2e}")
+        _gate_u0(precision, errs)
     eng.close()
 
 
@@ -100,15 +148,12 @@ def test_p2_fused_full_size_and_determinism(precision):
     eng, w = _engine(M, layers, precision, 4096, 50, 4)
     for seed in (1, 2):
         prob = sc.config_problem("P2", seed, instance_id=seed)
-        ref = oracle.solve(prob, w, sc.MODEL, contract="bf16w")
-        out = eng.step(prob)
+        ref = oracle.solve(prob, w, sc.MODEL, contract=CONTRACT[precision])
+        out = eng.step(prob, exports=True)
         assert out["rc"] == 0
-        e = u0_error(out["u0"], ref["u0"])
-        dJ = np.abs(out["J"] - ref["J"])
-        say(f"P2 fused {precision} seed {seed}: u0 err {e:.2e}, max |dJ| {dJ.max():.2e}, ess {out['ess']:.1f}")
-        assert e <= U0_GATE[precision]
-        if precision in FP32_LEVEL:
-            assert np.all(dJ <= 2e-5 * (np.abs(ref["J"]) + 50 * 50 + 1.0))
+        e, note = _gate(precision, prob, out, ref, f"P2 {precision} seed {seed}")
+        say(f"P2 fused {precision} seed {seed}: u0 err {e:.2e}, {note}, ess {out['ess']:.1f}")
+        assert e <= U0_TOL
     # same request twice (same explicit tick and nominal): bitwise equal
     U = oracle.hover_sequence(50, 0.37, 9.81)
     prob = sc.config_problem("P2", 3, instance_id=77, tick=5, U_nom=U)
@@ -127,10 +172,10 @@ def test_fused_ragged_shapes_and_gates(precision):
         prob = sc.make_problem(K, T, G, rot="haar", start="moving", seed=K + T, d_safe=1.0,
                                flags=flags, instance_id=K)
         ref = oracle.solve(prob, w, sc.MODEL, contract="bf16w")
-        out = eng.step(prob)
+        out = eng.step(prob, exports=True)
         assert out["rc"] == 0
-        e = u0_error(out["u0"], ref["u0"])
-        say(f"fused ragged K={K} T={T} G={G}: u0 err {e:.2e}")
+        e, note = _gate(precision, prob, out, ref, f"ragged K={K} T={T} G={G}")
+        say(f"fused ragged K={K} T={T} G={G}: u0 err {e:.2e}, {note}")
         assert e <= U0_TOL
     eng.close()
 
@@ -145,20 +190,19 @@ def test_fused_alignment_cost_two_hidden_layers():
         prob = sc.make_problem(512, 30, 4, rot="yaw", start="moving", seed=seed, d_safe=1.0, Q_vis=0.5,
                                instance_id=300 + seed)
         ref = oracle.solve(prob, w, sc.MODEL, contract="bf16w")
-        out = eng.step(prob)
+        out = eng.step(prob, exports=True)
         assert out["rc"] == 0
-        e = u0_error(out["u0"], ref["u0"])
-        dJ = np.abs(out["J"] - ref["J"])
-        say(f"fused Q_vis=0.5 seed {seed}: u0 err {e:.2e}, max |dJ| {dJ.max():.2e}")
+        e, note = _gate("bf16x3", prob, out, ref, f"Q_vis seed {seed}")
+        say(f"fused Q_vis=0.5 seed {seed}: u0 err {e:.2e}, {note}")
         assert e <= U0_TOL
-        assert np.all(dJ <= 2e-5 * (np.abs(ref["J"]) + prob["Q_sdf"] * prob["T"] + 1.0))
     eng.close()
 
 
-@pytest.mark.parametrize("precision", ["bf16", "fp8"])
+@pytest.mark.parametrize("precision", ["bf16", "fp8", "bf16x2"])
 def test_fused_low_precision_two_hidden_layers(precision):
-    """BF16 and FP8 on the two-hidden-layer decoder (the served shape), each
-    against its own contract; reported like the P1 variants."""
+    """BF16, FP8 and BF16X2 on the two-hidden-layer decoder (the served
+    shape), each against its own contract (near ties adjudicated for the
+    rounded ones)."""
     M = require_gpu()
     layers = (67, 256, 256, 256, 1)
     W, b = sc.xavier_weights(layers, seed=3)
@@ -166,20 +210,17 @@ def test_fused_low_precision_two_hidden_layers(precision):
              for s in (1, 2, 3)]
     scales = _act_scales(layers, W, b, probs) if precision == "fp8" else None
     eng, w = _engine(M, layers, precision, 384, 24, 4, act_scale=scales, wseed=3)
-    errs, jrel = [], []
+    errs = []
     for prob in probs:
-        ref = oracle.solve(prob, w, sc.MODEL, contract=CONTRACT[precision], act_scales=scales)
-        out = eng.step(prob)
+        ref = oracle.solve(prob, w, sc.MODEL, contract=CONTRACT[precision], act_scales=scales,
+                           near_ties=WINDOW.get(precision, False))
+        out = eng.step(prob, exports=True)
         assert out["rc"] == 0
-        errs.append(u0_error(out["u0"], ref["u0"]))
-        jrel.append(np.abs(out["J"] - ref["J"]) / (np.abs(ref["J"]) + prob["Q_sdf"] * prob["T"] + 1.0))
-    jr = np.concatenate(jrel)
-    say(f"fused {precision} 67-256-256-256-1: u0 err vs {CONTRACT[precision]} max {max(errs):.2e} "
-        f"median {np.median(errs):.2e}; relative cost error p50 {np.percentile(jr, 50):.1e} "
-        f"p90 {np.percentile(jr, 90):.1e}")
-    # observed: median 6.6e-4 (bf16), 2.9e-3 (fp8); cost p90 1.5e-6, 2.4e-5
-    assert np.median(errs) <= {"bf16": 3e-3, "fp8": 1e-2}[precision]
-    assert np.percentile(jr, 90) <= 1e-4
+        e, note = _gate(precision, prob, out, ref, f"{precision} 67-256-256-256-1")
+        say(f"fused {precision} 67-256-256-256-1 seed {prob['instance_id'] - 400}: u0 err vs "
+            f"{CONTRACT[precision]} {e:.2e}, {note}")
+        errs.append(e)
+    _gate_u0(precision, errs)
     eng.close()
 
 
@@ -193,19 +234,18 @@ def test_fused_h128_two_hidden_layers(precision):
     for K, T, G in ((600, 25, 3), (33, 7, 1)):
         prob = sc.make_problem(K, T, G, rot="haar", start="moving", seed=K, d_safe=1.0, instance_id=500 + K)
         ref = oracle.solve(prob, w, sc.MODEL, contract="bf16w")
-        out = eng.step(prob)
+        out = eng.step(prob, exports=True)
         assert out["rc"] == 0
-        e = u0_error(out["u0"], ref["u0"])
-        say(f"fused {precision} H=128 x2 K={K} T={T} G={G}: u0 err {e:.2e}")
+        e, note = _gate(precision, prob, out, ref, f"H=128 x2 K={K}")
+        say(f"fused {precision} H=128 x2 K={K} T={T} G={G}: u0 err {e:.2e}, {note}")
         assert e <= U0_TOL
     eng.close()
 
 
 @pytest.mark.parametrize("precision", ["bf16x3", "f16x2", "bf16x2", "bf16", "fp8"])
 def test_fused_h512_two_hidden_layers(precision):
-    """H = 512 (the large-fleet decoder shape, weights streamed through LDS):
-    BF16X3 at the float32 tolerance against bf16w, the others against their
-    contracts as on the other shapes.  G = 3 leaves a padding row in every
+    """H = 512 (the large-fleet decoder shape, weights streamed through LDS),
+    every kind against its contract.  G = 3 leaves a padding row in every
     block of 16; K = 300 a ragged last tile."""
     M = require_gpu()
     layers = (67, 512, 512, 512, 1)
@@ -214,30 +254,17 @@ def test_fused_h512_two_hidden_layers(precision):
              for s in (1, 2)]
     scales = _act_scales(layers, W, b, probs) if precision == "fp8" else None
     eng, w = _engine(M, layers, precision, 300, 16, 3, act_scale=scales, wseed=6, bias=0.2)
-    errs, jrel = [], []
+    errs = []
     for prob in probs:
-        ref = oracle.solve(prob, w, sc.MODEL, contract=CONTRACT[precision], act_scales=scales)
-        out = eng.step(prob)
+        ref = oracle.solve(prob, w, sc.MODEL, contract=CONTRACT[precision], act_scales=scales,
+                           near_ties=WINDOW.get(precision, False))
+        out = eng.step(prob, exports=True)
         assert out["rc"] == 0
-        errs.append(u0_error(out["u0"], ref["u0"]))
-        jrel.append(np.abs(out["J"] - ref["J"]) / (np.abs(ref["J"]) + prob["Q_sdf"] * prob["T"] + 1.0))
-    jr = np.concatenate(jrel)
-    say(f"fused {precision} 67-512-512-512-1: u0 err vs {CONTRACT[precision]} max {max(errs):.2e} "
-        f"median {np.median(errs):.2e}; relative cost error p50 {np.percentile(jr, 50):.1e} "
-        f"p90 {np.percentile(jr, 90):.1e} max {jr.max():.1e}")
-    if precision in FP32_LEVEL:
-        assert max(errs) <= U0_TOL
-        assert jr.max() <= 2e-5
-    elif precision == "bf16x2":
-        assert max(errs) <= U0_GATE["bf16x2"]
-    else:
-        # the bulk of the costs matches the contract closely; FP8 activation
-        # flips across 512-wide layers move a few costs by discrete steps that
-        # the softmax amplifies in u*_0 (observed: median 1.5e-2 for FP8,
-        # 9e-4 for BF16)
-        assert np.median(errs) <= {"bf16": 1e-2, "fp8": 5e-2}[precision]
-        assert np.percentile(jr, 50) <= 1e-5
-        assert np.percentile(jr, 90) <= 1e-4
+        e, note = _gate(precision, prob, out, ref, f"{precision} 67-512-512-512-1")
+        say(f"fused {precision} 67-512-512-512-1 seed {prob['instance_id'] - 600}: u0 err vs "
+            f"{CONTRACT[precision]} {e:.2e}, {note}")
+        errs.append(e)
+    _gate_u0(precision, errs)
     eng.close()
 
 
@@ -251,10 +278,10 @@ def test_fused_h512_one_hidden_layer_and_edges(precision):
     for K, T, G in ((1, 1, 1), (64, 12, 8), (17, 5, 5)):
         prob = sc.make_problem(K, T, G, rot="haar", start="moving", seed=K + 7 * T, d_safe=1.0, instance_id=700 + K)
         ref = oracle.solve(prob, w, sc.MODEL, contract="bf16w")
-        out = eng.step(prob)
+        out = eng.step(prob, exports=True)
         assert out["rc"] == 0
-        e = u0_error(out["u0"], ref["u0"])
-        say(f"fused {precision} H=512 x1 K={K} T={T} G={G}: u0 err {e:.2e}")
+        e, note = _gate(precision, prob, out, ref, f"H=512 x1 K={K}")
+        say(f"fused {precision} H=512 x1 K={K} T={T} G={G}: u0 err {e:.2e}, {note}")
         assert e <= U0_TOL
     eng.close()
 
@@ -264,8 +291,12 @@ def test_f16x2_weight_scaling(H):
     """F16X2 holds the bfloat16 weights in FP16 under a per-layer power of
     two: hidden layers scaled by 2^-12 (every weight below the FP16 normal
     range without the scale) and by 2^6 (activations of tens to hundreds in
-    the next layer) still match the bf16w contract at the float32
-    tolerance."""
+    the next layer) still match the bf16w contract: the per-query field
+    values element by element at the float32 tolerance, and u*_0 at
+    lambda = 1.  Costs here reach several hundred, where float32 cost
+    arithmetic alone moves u*_0 by ~1e-4 at lambda = 1; the plain FP32 path
+    on the same problem against the float32 network measures that floor, and
+    the gate is 1e-4 or twice the floor, whichever is larger."""
     M = require_gpu()
     layers = (67, H, H, H, 1)
     W, b = sc.xavier_weights(layers, seed=8, bias_scale=0.2)
@@ -275,17 +306,21 @@ def test_f16x2_weight_scaling(H):
     w = (W, b)
     eng = M.Engine(w, sc.MODEL, K_max=256, T_max=16, G_max=2, hidden=H, n_hidden=3,
                    precision="f16x2", path="fused", budget=512 << 20)
+    plain = M.Engine(w, sc.MODEL, K_max=256, T_max=16, G_max=2, hidden=H, n_hidden=3,
+                     precision="fp32", path="plain", budget=512 << 20)
     for seed in (1, 2):
-        # lambda = 10: with costs of several hundred, float32-level cost
-        # errors alone move u*_0 by ~1e-4 at lambda = 1; the per-rollout
-        # costs carry the check of the scaling
         prob = sc.make_problem(256, 16, 2, rot="haar", start="moving", seed=seed, d_safe=1.0,
-                               instance_id=800 + seed, lam=10.0)
+                               instance_id=800 + seed, lam=1.0)
         ref = oracle.solve(prob, w, sc.MODEL, contract="bf16w")
-        out = eng.step(prob)
+        out = eng.step(prob, exports=True)
         assert out["rc"] == 0
-        e = u0_error(out["u0"], ref["u0"])
-        jr = np.abs(out["J"] - ref["J"]) / (np.abs(ref["J"]) + prob["Q_sdf"] * prob["T"] + 1.0)
-        say(f"f16x2 H={H} scaled layers seed {seed}: u0 err {e:.2e}, max rel dJ {jr.max():.1e}")
-        assert e <= U0_TOL and jr.max() <= 2e-5
+        e, note = _gate("f16x2", prob, out, ref, f"f16x2 scaled H={H}")
+        ref32 = oracle.solve(prob, w, sc.MODEL, contract="fp32")
+        p32 = plain.step(prob)
+        assert p32["rc"] == 0
+        floor = u0_error(p32["u0"], ref32["u0"])
+        say(f"f16x2 H={H} scaled layers seed {seed} (lambda 1): u0 err {e:.2e}, {note}; "
+            f"plain FP32 on the same problem {floor:.2e}")
+        assert e <= max(U0_TOL, 2.0 * floor)
+    plain.close()
     eng.close()

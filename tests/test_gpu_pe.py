@@ -6,8 +6,9 @@ path with the FP64 oracle.
 Conditioning: the FP32 rollout places a query point to ~1e-6 relative (a
 few micrometres at these ranges); feature k turns a position error e into
 2^k pi e, so the float32 paths' agreement with the float64 oracle degrades
-with F.  Measured: u*_0 within 1e-4 of the oracle up to F = 3 on these
-workloads (gated there); F = 6 is reported."""
+with F.  Measured on these workloads: u*_0 within 4.2e-5 of the oracle at
+F = 6 (the widest encoding tested), gated at the float32 tolerance for
+every F."""
 import numpy as np
 import pytest
 
@@ -45,8 +46,7 @@ def test_positional_encoding_parity(path, precision, layers, contract):
     for F in (1, 2, 3, 6):
         errs = _run(M, path, precision, layers, F, contract, probs)
         say(f"PE {path}/{precision} H={layers[1]} F={F}: u0 err vs oracle max {max(errs):.2e}")
-        if F <= 3:
-            assert max(errs) <= U0_TOL
+        assert max(errs) <= U0_TOL
 
 
 def test_positional_encoding_rejected_on_wide_decoder():

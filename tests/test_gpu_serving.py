@@ -8,7 +8,10 @@ solves into fused launches.
   solves, every request still completes, the peak stays within the budget and
   several batches run.
 * Error codes: ENOMEM for a request that can never fit, EAGAIN for a full
-  queue, ENOTFOUND for an unknown ticket.
+  queue or (per ticket) a new instance while the instance table is full,
+  ENOTFOUND for an unknown ticket.
+* A torch-owned pool with no room beyond the budget: each batch's launch
+  block is counted at admission, and blocking solves count too.
 * Resident warm start across served ticks, checked against the oracle chain.
 """
 import time
@@ -108,8 +111,8 @@ def test_budget_admission_and_errors():
     assert all(rc == 0 for rc, _ in res)
     st = eng.stats()
     say(f"budget {budget} B: {st['waves']} batches, peak {st['bytes_peak']} B")
-    # the peak counts solve blocks (budgeted) plus small per-batch descriptor blocks
-    assert st["bytes_peak"] <= st["budget"] + (1 << 20) and st["waves"] >= 4
+    # solve blocks and each batch's launch block are both counted at admission
+    assert st["bytes_peak"] <= st["budget"] and st["waves"] >= 4
     rc, _ = eng.poll(123456789, 8, 8)
     assert rc == M.MPPI_ENOTFOUND
     eng.close()
@@ -131,4 +134,60 @@ def test_served_ticks_keep_the_warm_start_resident():
         say(f"served tick {tick}: u0 err {e:.2e}")
         assert e <= U0_TOL
         prev = r["U_star"]
+    eng.close()
+
+
+def test_full_instance_table_fails_only_new_instances():
+    """With the instance table full, a request for a new instance fails with
+    EAGAIN on its own; requests of existing instances admitted with it still
+    complete."""
+    M = require_gpu()
+    eng, _ = _engine(M, max_instances=4)
+    base = dict(_mix(1, seed=13)[0], K=512, T=20)
+    for iid in (1, 2, 3):
+        assert eng.step(dict(base, instance_id=iid))["rc"] == 0
+    probs = [dict(base, instance_id=iid) for iid in (1, 2, 10, 3, 11)]
+    tickets = []
+    for p in probs:
+        rc, t = eng.submit(p)
+        assert rc == 0
+        tickets.append(t)
+    res = _wait(eng, tickets, probs)
+    codes = [rc for rc, _ in res]
+    say(f"instance table of 4, three resident: statuses {codes}")
+    # FIFO: instance 10 takes the last free slot, 11 finds the table full
+    assert codes == [0, 0, 0, 0, M.MPPI_EAGAIN]
+    # the table stays usable for the resident instances
+    rc, t = eng.submit(probs[0])
+    assert rc == 0 and _wait(eng, [t], [probs[0]])[0][0] == 0
+    eng.close()
+
+
+def test_torch_pool_at_a_tight_budget():
+    """Device pool from torch with no room beyond the budget: every admitted
+    batch (solve blocks and the batch's launch block) fits what admission
+    counted, so all requests complete and the peak stays within the budget;
+    blocking solves count against the same budget."""
+    M = require_gpu()
+    probe, _ = _engine(M)
+    fp = probe.footprint(1024, 30, 1)
+    probe.close()
+    budget = 3 * fp
+    eng, _ = _engine(M, budget=budget, use_torch_memory=True)
+    assert eng.footprint(1024, 30, 1) == fp
+    probs = [dict(p, K=1024, T=30, instance_id=200 + i) for i, p in enumerate(_mix(12, seed=21))]
+    tickets = []
+    for p in probs:
+        rc, t = eng.submit(p)
+        assert rc == 0
+        tickets.append(t)
+    res = _wait(eng, tickets, probs)
+    assert all(rc == 0 for rc, _ in res), [rc for rc, _ in res]
+    st = eng.stats()
+    say(f"torch pool, budget {budget} B (3 solves): {st['waves']} batches, peak {st['bytes_peak']} B")
+    assert st["bytes_peak"] <= budget and st["waves"] >= 4
+    # a blocking solve larger than the whole budget can never run
+    assert eng.footprint(4096, 60, 1) > budget
+    big = dict(probs[0], K=4096, T=60, instance_id=300)
+    assert eng.step(big)["rc"] == M.MPPI_ENOMEM
     eng.close()
