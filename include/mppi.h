@@ -281,6 +281,23 @@ int mppi_batch_wait(mppi_engine* engine, mppi_batch* batch);
 int mppi_batch_results(mppi_engine* engine, mppi_batch* batch, mppi_result* results);
 int mppi_batch_destroy(mppi_engine* engine, mppi_batch* batch);
 
+/* For callers that cannot allocate device memory: code that sets up HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * The same blocking solve as mppi_step (same request, result, statuses and
+ * kernels, on the engine's stream), but the solve's device buffers live in a
+ * library-owned static device array of MPPI_NOALLOC_SCRATCH_BYTES per device
+ * instead of the engine's pool: the call allocates no device or pinned host
+ * memory (its host staging is pinned once in mppi_create) and does not count
+ * against the admission budget.  ENOMEM when the solve needs more than the
+ * array, i.e. when mppi_solve_footprint(engine, K, T, G) exceeds
+ * MPPI_NOALLOC_SCRATCH_BYTES; EINVAL when the result asks for samples,
+ * positions or field values (mppi_step exports them).  Every engine of the process on that
+ * device shares the array and it keeps the last call's contents: the library
+ * serialises these calls per device (overlapping calls wait; each process has
+ * its own array). */
+#define MPPI_NOALLOC_SCRATCH_BYTES (16u << 20)
+int mppi_step_noalloc(mppi_engine* engine, const mppi_request* request, mppi_result* result);
+
 #ifdef __cplusplus
 }
 #endif

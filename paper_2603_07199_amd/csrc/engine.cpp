@@ -148,12 +148,18 @@ struct mppi_engine {
   double* instU = nullptr;      // max_instances x T_max x 4
   uint32_t* instTick = nullptr;
   float* instCf = nullptr;      // MLP: max_instances x G_max x H folded latents (object permanence)
-  std::unordered_map<uint64_t, int> inst_map;
+  IdTable inst_map;             // instance id -> slot (sized at create)
   std::vector<InstInfo> inst;
   std::vector<double> hover;    // T_max x 4
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   char* pin[4] = {nullptr, nullptr, nullptr, nullptr};   // pinned staging per stream
   size_t pin_cap[4] = {0, 0, 0, 0};
+  // mppi_step_noalloc: the device's library-owned scratch array (address
+  // looked up at create) and pinned host staging sized at create for the
+  // largest solve the config accepts
+  void* scratch = nullptr;
+  char* pin_na = nullptr;
+  size_t pin_na_bytes = 0;
   mppi_stats stats{};
   std::atomic<int> sticky{0};
   std::mutex mu;                // guards everything above and below
@@ -281,9 +287,9 @@ int validate(const mppi_engine* e, const mppi_request* r, double Lo[16]) {
 
 // ---------------------------------------------------------------- instances
 int acquire_slot(mppi_engine* e, uint64_t id, int* slot) {
-  auto it = e->inst_map.find(id);
-  if (it != e->inst_map.end()) {
-    *slot = it->second;
+  const int found = e->inst_map.find(id);
+  if (found >= 0) {
+    *slot = found;
     return MPPI_OK;
   }
   if ((int)e->inst.size() >= e->cfg.max_instances) return MPPI_EAGAIN;
@@ -294,8 +300,8 @@ int acquire_slot(mppi_engine* e, uint64_t id, int* slot) {
   info.id = id;
   info.U_len = e->cfg.T_max;
   info.busy = false;
-  e->inst.push_back(info);
-  e->inst_map[id] = s;
+  e->inst.push_back(info);        // capacity reserved at create: no reallocation
+  e->inst_map.insert(id, s);
   *slot = s;
   return MPPI_OK;
 }
@@ -307,8 +313,8 @@ bool gates_cached_ok(const mppi_engine* e, const mppi_request* r) {
   for (int g = 0; g < r->G; ++g)
     if (!r->gates[g].z) need |= 1u << g;
   if (!need) return true;
-  auto it = e->inst_map.find(r->instance_id);
-  return it != e->inst_map.end() && (e->inst[it->second].seen & need) == need;
+  const int slot = e->inst_map.find(r->instance_id);
+  return slot >= 0 && (e->inst[slot].seen & need) == need;
 }
 
 int tile_rollouts(const mppi_engine* e, int G) {
@@ -899,6 +905,7 @@ int mppi_create(const mppi_config* cfg, const mppi_sdf_weights* w, mppi_engine**
     if (e->instU) hipFree(e->instU);
     if (e->instTick) hipFree(e->instTick);
     if (e->instCf) hipFree(e->instCf);
+    if (e->pin_na) hipHostFree(e->pin_na);
     return rc;
   };
   hipStream_t s0 = (hipStream_t)c.stream;
@@ -935,6 +942,21 @@ int mppi_create(const mppi_config* cfg, const mppi_sdf_weights* w, mppi_engine**
     const size_t cf = sizeof(float) * nI * c.G_max * e->H;
     if (hipMalloc(&e->instCf, cf) != hipSuccess) return bail(MPPI_ENOMEM);
     if (hipMemset(e->instCf, 0, cf) != hipSuccess) return bail(MPPI_EDEVICE);
+  }
+  e->inst.reserve((size_t)c.max_instances);
+  e->inst_map.reset(c.max_instances);
+  // the no-allocation entry point's device scratch (this device is current)
+  // and its host staging: uploads, launch block and read-back of one solve
+  if (scratch_device_address(c.device, &e->scratch) != hipSuccess) return bail(MPPI_EDEVICE);
+  {
+    const int R = e->fused ? tile_rollouts(e.get(), c.G_max) : 1;
+    const uint64_t nt = e->fused ? (uint64_t)(c.K_max + R - 1) / R : 0;
+    e->pin_na_bytes = align_up(layout_for(e.get(), c.K_max, c.T_max, c.G_max).upload_bytes) +
+                      align_up(sizeof(SolveDesc)) + align_up(sizeof(int2) * nt) + kAlign +
+                      align_up(sizeof(double) * (4 * (uint64_t)c.T_max + RES_SCALARS)) +
+                      align_up(sizeof(float) * (uint64_t)c.K_max) + align_up(sizeof(double) * (uint64_t)c.K_max);
+    if (hipHostMalloc((void**)&e->pin_na, e->pin_na_bytes, hipHostMallocDefault) != hipSuccess)
+      return bail(MPPI_ENOMEM);
   }
   e->hover.assign((size_t)4 * c.T_max, 0.0);
   // a new instance starts from hover: thrust m g at zero body rate, or zero
@@ -979,6 +1001,7 @@ int mppi_destroy(mppi_engine* e) {
   if (e->instCf) hipFree(e->instCf);
   for (char* p : e->pin)
     if (p) hipHostFree(p);
+  if (e->pin_na) hipHostFree(e->pin_na);
   delete e;
   return MPPI_OK;
 }
@@ -1210,6 +1233,90 @@ int mppi_batch_destroy(mppi_engine* e, mppi_batch* b) {
   return MPPI_OK;
 }
 
+int mppi_step_noalloc(mppi_engine* e, const mppi_request* r, mppi_result* out) {
+  if (!e || !r || !out || !out->U_star) return MPPI_EINVAL;
+  if (out->samples || out->positions || out->sdf) return MPPI_EINVAL;
+  if (e->sticky.load()) return MPPI_EDEVICE;
+  std::lock_guard<std::mutex> lk(e->mu);
+  // one user of this device's scratch at a time within the process
+  std::lock_guard<std::mutex> dk(scratch_use_mutex(e->dev));
+  hipSetDevice(e->dev);
+  const uint64_t t_submit = now_ns();
+  double Lo[16];
+  int rc = validate(e, r, Lo);
+  if (rc != MPPI_OK) return rc;
+  const int K = r->K, T = r->T, G = r->G;
+  // the solve's block, then on the fused path its launch block (descriptor,
+  // tile list, work counter), all inside the scratch array
+  Solve s;
+  s.K = K;
+  s.T = T;
+  s.G = G;
+  s.flags = r->flags;
+  s.want_w = out->weights != nullptr;
+  s.want_J = out->costs != nullptr;
+  s.exports = false;
+  s.lay = layout_for(e, K, T, G);
+  const int R = e->fused ? tile_rollouts(e, G) : 1;
+  const int nt = e->fused ? (K + R - 1) / R : 0;
+  const uint64_t o_tiles = align_up(sizeof(SolveDesc));
+  const uint64_t o_cnt = o_tiles + align_up(sizeof(int2) * (uint64_t)nt);
+  const uint64_t aux_bytes = e->fused ? o_cnt + kAlign : 0;
+  if (s.lay.total + aux_bytes > kScratchBytes) return MPPI_ENOMEM;
+  rc = acquire_slot(e, r->instance_id, &s.slot);
+  if (rc != MPPI_OK) return rc;
+  if (e->inst[s.slot].busy) return MPPI_EAGAIN;
+  if (!gates_cached_ok(e, r)) return MPPI_EINVAL;
+  char* base = (char*)e->scratch;
+  char* host = e->pin_na;
+  const uint64_t up = align_up(s.lay.upload_bytes);
+  char* aux_host = host + up;
+  char* rb = aux_host + align_up(aux_bytes);
+  pack_solve(e, r, &s, Lo, base, host);
+  hipStream_t st = e->streams[0];
+  HIPCHK(e, hipMemcpyAsync(base, host, s.lay.upload_bytes, hipMemcpyHostToDevice, st));
+  if (e->fused) {
+    memset(aux_host, 0, aux_bytes);
+    memcpy(aux_host, &s.desc, sizeof(SolveDesc));
+    int2* tl = (int2*)(aux_host + o_tiles);
+    for (int t = 0; t < nt; ++t) tl[t] = int2{0, t * R};
+    char* ab = base + s.lay.total;
+    HIPCHK(e, hipMemcpyAsync(ab, aux_host, aux_bytes, hipMemcpyHostToDevice, st));
+    const SolveDesc* dd = (const SolveDesc*)ab;
+    HIPCHK(e, launch_fold(dd, 1, G, e->dw, st));
+    FusedBatch fb{dd, (const int2*)(ab + o_tiles), nt, (uint32_t*)(ab + o_cnt)};
+    HIPCHK(e, launch_fused(fb, 1, e->dw, T, G, nt, st, nullptr, nullptr));
+  } else {
+    PlainShape shp{K, T, G, e->cfg.sdf_kind};
+    HIPCHK(e, launch_plain((const SolveDesc*)(base + s.lay.desc), shp, e->dw, st, nullptr, nullptr));
+  }
+  // read-back into the pinned staging: result block, costs, weights
+  const size_t nres = 4 * (size_t)T + RES_SCALARS;
+  double* res = (double*)rb;
+  float* Jh = (float*)(rb + align_up(sizeof(double) * nres));
+  double* wh = (double*)((char*)Jh + align_up(sizeof(float) * (uint64_t)K));
+  HIPCHK(e, hipMemcpyAsync(res, base + s.lay.result, sizeof(double) * nres, hipMemcpyDeviceToHost, st));
+  if (s.want_J) HIPCHK(e, hipMemcpyAsync(Jh, base + s.lay.J, sizeof(float) * K, hipMemcpyDeviceToHost, st));
+  if (s.want_w) HIPCHK(e, hipMemcpyAsync(wh, base + s.lay.wn, sizeof(double) * K, hipMemcpyDeviceToHost, st));
+  HIPCHK(e, hipStreamSynchronize(st));
+  const double* sc = res + 4 * T;
+  out->status = (int32_t)sc[RES_STATUS];
+  out->tick_used = (uint32_t)sc[RES_TICK];
+  memcpy(out->U_star, res, sizeof(double) * 4 * T);
+  for (int c = 0; c < 4; ++c) out->u0[c] = sc[RES_U0 + c];
+  out->J_min = sc[RES_JMIN];
+  out->log_eta = sc[RES_LOGETA];
+  out->ess = sc[RES_ESS];
+  if (s.want_w) memcpy(out->weights, wh, sizeof(double) * K);
+  if (s.want_J)
+    for (int k = 0; k < K; ++k) out->costs[k] = (double)Jh[k] + s.C0;
+  out->t_submit_ns = out->t_admit_ns = t_submit;
+  out->t_done_ns = now_ns();
+  if (out->status == MPPI_OK && !(s.flags & MPPI_REQ_NO_SHIFT)) e->inst[s.slot].U_len = T;
+  e->stats.completed++;
+  return out->status;
+}
+
 }  // extern "C"
 
 namespace {
@@ -1254,8 +1361,8 @@ void scheduler_loop(mppi_engine* e) {
     if (!e->stop && !e->sticky.load() && (int)e->inflight.size() < nstreams) {
       const uint64_t cap = e->cfg.wave_queries_max ? e->cfg.wave_queries_max : (1ull << 21);
       auto adm = e->adm->admit([&](uint64_t id) {
-        auto it = e->inst_map.find(id);
-        return it != e->inst_map.end() && e->inst[it->second].busy;
+        const int slot = e->inst_map.find(id);
+        return slot >= 0 && e->inst[slot].busy;
       }, cap);
       // a request that cannot run fails on its own instead of failing the
       // batch it was admitted with: an unobserved gate without a cached
@@ -1267,7 +1374,7 @@ void scheduler_loop(mppi_engine* e) {
         int fail = MPPI_OK;
         if (!gates_cached_ok(e, r)) {
           fail = MPPI_EINVAL;
-        } else if (!e->inst_map.count(r->instance_id)) {
+        } else if (!e->inst_map.contains(r->instance_id)) {
           if ((int)e->inst.size() + new_slots >= e->cfg.max_instances) fail = MPPI_EAGAIN;
           else ++new_slots;
         }

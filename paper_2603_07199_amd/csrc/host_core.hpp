@@ -73,6 +73,59 @@ class Arena {
   std::map<uint64_t, uint64_t> free_;
 };
 
+// Instance id -> slot map with its storage sized once (open addressing,
+// linear probing, a power-of-two table of at least twice the capacity), so
+// lookups and inserts never allocate.
+class IdTable {
+ public:
+  void reset(int capacity) {
+    size_t n = 16;
+    while (n < 2 * (size_t)(capacity > 0 ? capacity : 1)) n <<= 1;
+    keys_.assign(n, 0);
+    vals_.assign(n, -1);
+    mask_ = n - 1;
+    cap_ = capacity;
+    count_ = 0;
+  }
+  int find(uint64_t id) const {
+    for (size_t i = mix(id) & mask_;; i = (i + 1) & mask_) {
+      if (vals_[i] < 0) return -1;
+      if (keys_[i] == id) return vals_[i];
+    }
+  }
+  bool contains(uint64_t id) const { return find(id) >= 0; }
+  // false when the table already holds `capacity` ids (id new)
+  bool insert(uint64_t id, int value) {
+    size_t i = mix(id) & mask_;
+    for (; vals_[i] >= 0; i = (i + 1) & mask_)
+      if (keys_[i] == id) {
+        vals_[i] = value;
+        return true;
+      }
+    if (count_ >= cap_) return false;
+    keys_[i] = id;
+    vals_[i] = value;
+    ++count_;
+    return true;
+  }
+  int size() const { return count_; }
+
+ private:
+  // 64-bit finaliser of MurmurHash3 (public domain): spreads sequential ids
+  static uint64_t mix(uint64_t x) {
+    x ^= x >> 33;
+    x *= 0xff51afd7ed558ccdull;
+    x ^= x >> 33;
+    x *= 0xc4ceb9fe1a85ec53ull;
+    x ^= x >> 33;
+    return x;
+  }
+  std::vector<uint64_t> keys_;
+  std::vector<int> vals_;
+  size_t mask_ = 0;
+  int cap_ = 0, count_ = 0;
+};
+
 // Byte layout of one solve's device block (descriptor, request data, buffers).
 struct SolveLayout {
   uint64_t desc, U, Rt, base, z, los;                // request part (uploaded)

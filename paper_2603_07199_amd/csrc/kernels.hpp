@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
 #include <vector>
 
 #include "../../include/mppi.h"
@@ -57,5 +58,14 @@ void pack_pe_weights_f16(int H, int n_feat, int ld, const float* W0, std::vector
 int pack_lowp_weights(int precision, int H, int n_hidden, const mppi_sdf_weights* w,
                       std::vector<uint8_t>& blob, std::vector<float>& w_scale,
                       std::vector<float>& a_scale, std::vector<float>& a_inv);
+
+// Library-owned device scratch of the entry point that allocates nothing
+// (mppi_step_noalloc), one array per device for the life of the process.
+constexpr size_t kScratchBytes = (size_t)MPPI_NOALLOC_SCRATCH_BYTES;
+// Device address of the array on `device` (which the caller has made
+// current), looked up once per device.
+hipError_t scratch_device_address(int device, void** out);
+// Serialises the calls that use the array of `device` within the process.
+std::mutex& scratch_use_mutex(int device);
 
 }  // namespace mppi

@@ -95,7 +95,10 @@ class mppi_stats(C.Structure):
 EXPORTED = ["mppi_create", "mppi_destroy", "mppi_step", "mppi_submit", "mppi_poll",
             "mppi_drain", "mppi_get_stats", "mppi_reset_stats", "mppi_status_str",
             "mppi_solve_footprint", "mppi_batch_create", "mppi_batch_run", "mppi_batch_wait",
-            "mppi_batch_results", "mppi_batch_destroy"]
+            "mppi_batch_results", "mppi_batch_destroy", "mppi_step_noalloc"]
+
+# MPPI_NOALLOC_SCRATCH_BYTES of include/mppi.h
+NOALLOC_SCRATCH_BYTES = 16 << 20
 
 _lib = None
 
@@ -127,9 +130,10 @@ def load_library(path=LIB_PATH):
     lib.mppi_batch_wait.argtypes = [C.c_void_p, C.c_void_p]
     lib.mppi_batch_results.argtypes = [C.c_void_p, C.c_void_p, P(mppi_result)]
     lib.mppi_batch_destroy.argtypes = [C.c_void_p, C.c_void_p]
+    lib.mppi_step_noalloc.argtypes = [C.c_void_p, P(mppi_request), P(mppi_result)]
     for name in ("mppi_create", "mppi_destroy", "mppi_step", "mppi_submit", "mppi_poll",
                  "mppi_drain", "mppi_get_stats", "mppi_batch_create", "mppi_batch_run",
-                 "mppi_batch_wait", "mppi_batch_results", "mppi_batch_destroy"):
+                 "mppi_batch_wait", "mppi_batch_results", "mppi_batch_destroy", "mppi_step_noalloc"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -274,6 +278,16 @@ def mppi_step(handle, prob, weights=True, costs=True, exports=False):
     return out
 
 
+def mppi_step_noalloc(handle, prob, weights=True, costs=True):
+    """mppi_step on the library's static device scratch (no allocation)."""
+    rq = _Request(prob)
+    rs = _Result(prob["K"], prob["T"], weights, costs, False)
+    rc = load_library().mppi_step_noalloc(handle, C.byref(rq.req), C.byref(rs.res))
+    out = rs.as_dict()
+    out["rc"] = rc
+    return out
+
+
 def mppi_submit(handle, prob):
     rq = _Request(prob)
     t = C.c_uint64()
@@ -387,6 +401,9 @@ class Engine:
 
     def step(self, prob, **kw):
         return mppi_step(self.h, prob, **kw)
+
+    def step_noalloc(self, prob, **kw):
+        return mppi_step_noalloc(self.h, prob, **kw)
 
     def submit(self, prob):
         return mppi_submit(self.h, prob)

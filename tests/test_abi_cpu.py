@@ -184,6 +184,14 @@ int main() {
   q4.unreserve(600);
   adm = q4.admit(none);
   assert(adm.size() == 1 && q4.in_use() == 500);
+  // instance id table: sized once, finds what was inserted, refuses past capacity
+  IdTable ids;
+  ids.reset(100);
+  for (int i = 0; i < 100; ++i) assert(ids.insert(1000003ull * i + (1ull << 40), i));
+  assert(!ids.insert(7, 100) && ids.size() == 100);
+  for (int i = 0; i < 100; ++i) assert(ids.find(1000003ull * i + (1ull << 40)) == i);
+  assert(ids.find(7) == -1 && !ids.contains(8));
+  assert(ids.insert(1ull << 40, 55) && ids.find(1ull << 40) == 55 && ids.size() == 100);   // existing id
   // layout: regions are disjoint, aligned, and grow with K, T, G
   SolveLayout L = solve_layout(4096, 50, 4, 256, false, 0);
   assert(L.total % kAlign == 0 && L.upload_bytes <= L.result);
