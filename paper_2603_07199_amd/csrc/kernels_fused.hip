@@ -123,6 +123,28 @@ __device__ __forceinline__ float softplus_act(float x) {
   else return softplus_fast(x);
 }
 
+// Four softplus evaluations in the arithmetic of softplus_fast /
+// softplus_capped (CAP), stage by stage: the four base-2 exponentials, then
+// the four logarithms, then the four sums.  The stages are kept apart for
+// the scheduler, so the four independent chains overlap their latencies
+// instead of running one after another through one temporary.
+template <bool CAP>
+__device__ __forceinline__ void softplus4(const float (&x)[4], float (&v)[4]) {
+  float e[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) e[i] = __builtin_amdgcn_exp2f(-fabsf(x[i]) * 1.4426950408889634f);
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) e[i] = __builtin_amdgcn_logf(1.0f + e[i]);
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int b = __float_as_int(x[i]);
+    const int r = CAP ? (b > 0 ? (b < 0x477FDF00 ? b : 0x477FDF00) : 0) : (b > 0 ? b : 0);
+    v[i] = fmaf(e[i], 0.6931471805599453f, __int_as_float(r));
+  }
+}
+
 // LDS activation row stride in elements (bf16) / bytes (fp8): the pad keeps
 // 16-byte operand reads of 16 consecutive rows on distinct banks.
 template <int H> __host__ __device__ constexpr int act_stride_bf16() { return H + 8; }
@@ -683,8 +705,13 @@ __device__ __forceinline__ void products(const char* in, uint32_t boff, const fl
 // SIMD's pair of waves take about equally long: a products-first wave takes
 // kL1B blocks (its products join the end of its matrix-core phase), a
 // vector-first wave kL1A blocks (products at the start of its vector phase).
-template <int H> struct L1Split {
-  static constexpr int B = H >= 256 ? 3 : 1;               // blocks per products-first wave
+// With split activations (BF16X2/BF16X3/F16X2) the vector-first waves of a
+// two-hidden-layer decoder carry the costly operand splits of the first
+// hidden layer, so the products-first waves take 3 of every 4 layer-1
+// blocks; with one activation term (BF16, FP8) the split is one conversion
+// and the blocks are shared equally.
+template <int P, int H> struct L1Split {
+  static constexpr int B = (H >= 256 && PrecTraits<P>::splits > 1) ? 3 : H / 16 / kWaves;  // per products-first wave
   static constexpr int A = (H / 16 - (kWaves / 2) * B) / (kWaves / 2);
   static_assert(A >= 0 && (kWaves / 2) * (A + B) * 16 == H, "layer-1 split");
   // first block of wave w (waves 4-7 products first, 0-3 vector first)
@@ -754,12 +781,11 @@ __device__ __forceinline__ void vector_work(const f32x4 (&acc)[MB], const f32x4 
   float op = 0.0f;
 #pragma unroll
   for (int mb = 0; mb < MB; ++mb) {
-    float v[4];
+    float xs[4], v[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const float x = pre_act<P>(acc[mb][i], scale_own, PT::fp8 ? hb[OWN * H + e0 + 16 * mb + i] : 0.0f);
-      v[i] = OWN + 1 < NHH ? softplus_act<P>(x) : softplus_fast(x);
-    }
+    for (int i = 0; i < 4; ++i)
+      xs[i] = pre_act<P>(acc[mb][i], scale_own, PT::fp8 ? hb[OWN * H + e0 + 16 * mb + i] : 0.0f);
+    softplus4<OWN + 1 < NHH && PT::f16>(xs, v);
     if constexpr (OWN + 1 < NHH) {
       put_act<P, H>(out, eoff + act_off<P, H>(0, 16 * mb), v, PT::fp8 ? w.a_inv[OWN + 1] : 1.0f);
     } else {
@@ -772,9 +798,9 @@ __device__ __forceinline__ void vector_work(const f32x4 (&acc)[MB], const f32x4 
   const uint32_t loff = act_off<P, H>(nl, 16 * b0 + 4 * h);
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
+    const float xs[4] = {x[j][0], x[j][1], x[j][2], x[j][3]};
     float v[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) v[i] = softplus_act<P>(x[j][i]);
+    softplus4<PT::f16>(xs, v);
     put_act<P, H>(l1out, loff + act_off<P, H>(0, 16 * j), v, PT::fp8 ? w.a_inv[0] : 1.0f);
     if (j & 1) sched_fence();
   }
@@ -794,7 +820,7 @@ __device__ __forceinline__ void pipeline_step(const Views& V, const DeviceWeight
                                               int nl, float scale_own, const FragT<P> (&wreg)[MB][H / 32],
                                               f32x4 (&acc)[2][MB], const float* pts_prev, const float* pts_cur,
                                               const char* fs_prev, const char* fs_cur,
-                                              f32x4 (&x1c)[L1Split<H>::A > 0 ? L1Split<H>::A : 1]) {
+                                              f32x4 (&x1c)[L1Split<P, H>::A > 0 ? L1Split<P, H>::A : 1]) {
   constexpr int WPL = kWaves / NHH;
   constexpr size_t AB = act_buf_bytes<P, H>();
   const char* in = V.act + (2 * OWN + PAR) * AB;
@@ -803,11 +829,11 @@ __device__ __forceinline__ void pipeline_step(const Views& V, const DeviceWeight
   float* op = V.opart + (1 - PAR) * WPL * kRows * 4;
   const uint32_t boff = act_off<P, H>(nl, 8 * h);
   BFragT<P> b0[PrecTraits<P>::splits];
-  const int l1b = L1Split<H>::first(wave);
+  const int l1b = L1Split<P, H>::first(wave);
   if constexpr (MFIRST) {
     // matrix-core phase: owned layer, then this wave's layer-1 blocks of
     // block s-1; vector phase after it
-    constexpr int NB = L1Split<H>::B;
+    constexpr int NB = L1Split<P, H>::B;
     f32x4 x1[NB > 0 ? NB : 1];
     read_operands<P, H>(in, boff, 0, b0);
     products<P, H, OWN, MB>(in, boff, V.hb, gw, h, wreg, b0, acc[PAR]);
@@ -819,7 +845,7 @@ __device__ __forceinline__ void pipeline_step(const Views& V, const DeviceWeight
     // step), then the matrix-core phase, which ends with the layer-1
     // products of block s for the next step: no matrix-core instruction in
     // the vector phase, where it would queue behind the other wave's products
-    constexpr int NB = L1Split<H>::A;
+    constexpr int NB = L1Split<P, H>::A;
     read_operands<P, H>(in, boff, 0, b0);
     vector_work<P, H, NHH, OWN, MB, NB>(acc[1 - PAR], x1c, out, l1out, op, V.hb, V.wo, w, l1b, gw, h, nl, scale_own);
     sched_fence();
@@ -843,9 +869,9 @@ __device__ __forceinline__ void decoder_tile(const Views& V, const SolveDesc& d,
   for (int p = 0; p < 2; ++p)
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb) acc[p][mb] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-  f32x4 x1c[L1Split<H>::A > 0 ? L1Split<H>::A : 1];
+  f32x4 x1c[L1Split<P, H>::A > 0 ? L1Split<P, H>::A : 1];
 #pragma unroll
-  for (int j = 0; j < (L1Split<H>::A > 0 ? L1Split<H>::A : 1); ++j) x1c[j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  for (int j = 0; j < (L1Split<P, H>::A > 0 ? L1Split<P, H>::A : 1); ++j) x1c[j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
   // Gate-frame points of block b live in slot b % 3: in step s wave 1 writes
   // block s+1 while the layer-1 products read blocks s-1 and s.  The edge
   // work goes to two waves that run their vector work first and have slack at
@@ -1239,12 +1265,13 @@ __device__ __forceinline__ void wide_l1_half(const Views& V, const float (&pt)[4
   const int n0 = 32 * ks + 16 * par + 4 * hq;
   const float4 c = *(const float4*)(V.cf + (int)pt[3] * wide_cf_stride<H>() + n0);
   const float cc[4] = {c.x, c.y, c.z, c.w};
-  float v[4];
+  float xs[4], v[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const float4 w = *(const float4*)(V.w1p + 4 * (n0 + i));
-    v[i] = softplus_act<P>(fmaf(w.x, pt[0], fmaf(w.y, pt[1], fmaf(w.z, pt[2], cc[i]))));
+    xs[i] = fmaf(w.x, pt[0], fmaf(w.y, pt[1], fmaf(w.z, pt[2], cc[i])));
   }
+  softplus4<PrecTraits<P>::f16>(xs, v);
   wide_put_half<P>(x, lane, par, v, inv);
 }
 
@@ -1259,8 +1286,10 @@ __device__ __forceinline__ void wide_epi_half(const f32x4& acc, const float* hb,
   float4 bb = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
   if constexpr (PrecTraits<P>::fp8) bb = *(const float4*)(hb + 32 * ks + 16 * par + 4 * hq);
   const float bv[4] = {bb.x, bb.y, bb.z, bb.w};
+  float xs[4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) v[i] = softplus_act<P>(pre_act<P>(acc[i], scale, bv[i]));
+  for (int i = 0; i < 4; ++i) xs[i] = pre_act<P>(acc[i], scale, bv[i]);
+  softplus4<PrecTraits<P>::f16>(xs, v);
   wide_put_half<P>(x, lane, par, v, inv);
 }
 
@@ -1333,8 +1362,12 @@ __device__ __forceinline__ void wide_output_part(const Views& V, const f32x4 (&a
     float4 bb = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     if constexpr (PrecTraits<P>::fp8) bb = *(const float4*)(hb + n0);
     const float ow[4] = {o4.x, o4.y, o4.z, o4.w}, bv[4] = {bb.x, bb.y, bb.z, bb.w};
+    float xs[4], v[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) op = fmaf(ow[i], softplus_fast(pre_act<P>(acc[m][i], scale, bv[i])), op);
+    for (int i = 0; i < 4; ++i) xs[i] = pre_act<P>(acc[m][i], scale, bv[i]);
+    softplus4<false>(xs, v);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) op = fmaf(ow[i], v[i], op);
   }
   op += __shfl_xor(op, 16, 64);
   op += __shfl_xor(op, 32, 64);

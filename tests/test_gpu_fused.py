@@ -163,6 +163,24 @@ def test_p2_fused_full_size_and_determinism(precision):
     eng.close()
 
 
+def test_p2_bf16_full_size_adjudicated():
+    """The single-term BF16 kind on the full paper-scale workload (K = 4096,
+    T = 50, four gates, 67-256-256-256-1): every one of the 204,800 field
+    values is a legitimate rounding, the costs match, and u*_0 is within 1e-4
+    of the oracle's update for the device's roundings."""
+    M = require_gpu()
+    layers = (67, 256, 256, 256, 1)
+    eng, w = _engine(M, layers, "bf16", 4096, 50, 4)
+    prob = sc.config_problem("P2", 1, instance_id=1)
+    ref = oracle.solve(prob, w, sc.MODEL, contract="bf16", near_ties=True)
+    out = eng.step(prob, exports=True)
+    assert out["rc"] == 0
+    e, note = _gate("bf16", prob, out, ref, "P2 bf16")
+    say(f"P2 fused bf16 seed 1: u0 err vs bf16 {e:.2e}, {note}, ess {out['ess']:.1f}")
+    assert e <= U0_TOL
+    eng.close()
+
+
 @pytest.mark.parametrize("precision", FP32_LEVEL)
 def test_fused_ragged_shapes_and_gates(precision):
     M = require_gpu()
