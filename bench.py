@@ -81,10 +81,13 @@ def _mfma_flops_per_query(layers):
 
 
 # Vector-unit work of the decoder: one softplus per hidden neuron and query
-# (768 at 67-256-256-256-1), 12 lane-slots each (two quarter-rate
-# transcendentals = 8, four full-rate operations).  Peak: 256 CUs x 4 SIMDs x
-# 16 lanes x 2.4 GHz of non-packed float32 issue.
-SOFTPLUS_LANE_SLOTS = 12
+# (768 at 67-256-256-256-1) of 8 lane-slots each: four full-rate operations
+# (scale, 1 + e, max, fused multiply-add) and two transcendentals (base-2
+# exponential and logarithm) that issue at half rate on gfx950 (measured:
+# the counters give 8 cycles per wave64 transcendental against 4 for the
+# other vector operations).  Peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz of
+# non-packed float32 issue.
+SOFTPLUS_LANE_SLOTS = 8
 VALU_PEAK_LANE_SLOTS = 256 * 4 * 16 * 2.4e9
 
 

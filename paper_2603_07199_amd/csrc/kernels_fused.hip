@@ -1265,13 +1265,12 @@ __device__ __forceinline__ void wide_l1_half(const Views& V, const float (&pt)[4
   const int n0 = 32 * ks + 16 * par + 4 * hq;
   const float4 c = *(const float4*)(V.cf + (int)pt[3] * wide_cf_stride<H>() + n0);
   const float cc[4] = {c.x, c.y, c.z, c.w};
-  float xs[4], v[4];
+  float v[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const float4 w = *(const float4*)(V.w1p + 4 * (n0 + i));
-    xs[i] = fmaf(w.x, pt[0], fmaf(w.y, pt[1], fmaf(w.z, pt[2], cc[i])));
+    v[i] = softplus_act<P>(fmaf(w.x, pt[0], fmaf(w.y, pt[1], fmaf(w.z, pt[2], cc[i]))));
   }
-  softplus4<PrecTraits<P>::f16>(xs, v);
   wide_put_half<P>(x, lane, par, v, inv);
 }
 
@@ -1286,10 +1285,8 @@ __device__ __forceinline__ void wide_epi_half(const f32x4& acc, const float* hb,
   float4 bb = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
   if constexpr (PrecTraits<P>::fp8) bb = *(const float4*)(hb + 32 * ks + 16 * par + 4 * hq);
   const float bv[4] = {bb.x, bb.y, bb.z, bb.w};
-  float xs[4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) xs[i] = pre_act<P>(acc[i], scale, bv[i]);
-  softplus4<PrecTraits<P>::f16>(xs, v);
+  for (int i = 0; i < 4; ++i) v[i] = softplus_act<P>(pre_act<P>(acc[i], scale, bv[i]));
   wide_put_half<P>(x, lane, par, v, inv);
 }
 
@@ -1362,12 +1359,8 @@ __device__ __forceinline__ void wide_output_part(const Views& V, const f32x4 (&a
     float4 bb = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     if constexpr (PrecTraits<P>::fp8) bb = *(const float4*)(hb + n0);
     const float ow[4] = {o4.x, o4.y, o4.z, o4.w}, bv[4] = {bb.x, bb.y, bb.z, bb.w};
-    float xs[4], v[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) xs[i] = pre_act<P>(acc[m][i], scale, bv[i]);
-    softplus4<false>(xs, v);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) op = fmaf(ow[i], v[i], op);
+    for (int i = 0; i < 4; ++i) op = fmaf(ow[i], softplus_fast(pre_act<P>(acc[m][i], scale, bv[i])), op);
   }
   op += __shfl_xor(op, 16, 64);
   op += __shfl_xor(op, 32, 64);
