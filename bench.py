@@ -5,7 +5,8 @@ rollouts, horizon T = 50 (dt = 0.02 s), 4 gates, Gate-SDF decoder
 67 -> 256 -> 256 -> 256 -> 1, seeded synthetic inputs (see scenarios/).
 With --workload fleet: the large served fleet instead, 1024 instances of
 K = 2048, T = 40, 8 gates, decoder 67 -> 512 -> 512 -> 512 -> 1, one step =
-one control tick of every instance.
+one control tick of every instance; --workload small: one small solve
+(K = 256, T = 20, one gate, 67 -> 128 -> 128 -> 1).
 The requests are staged into device memory before timing (mppi_batch_*), so
 the timed region holds kernel launches only; each instance's warm start and
 RNG tick advance on the device from step to step.
@@ -22,7 +23,7 @@ probes' p99 stays under 5 ms) and the FP64 oracle timed on the host cores
 
     python bench.py [--steps K] [--warmup W] [--path fused|plain]
                     [--precision bf16|bf16x3|f16x2|bf16x2|fp8|fp32] [--batch B]
-                    [--workload paper|fleet]
+                    [--workload paper|fleet|small]
 """
 from __future__ import annotations
 
@@ -45,7 +46,7 @@ import scenarios as sc  # noqa: E402
 HBM_PEAK = 8.0e12
 PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "bf16x2": 2500.0, "bf16x3": 2500.0, "f16x2": 2500.0, "fp8": 5000.0}
 # the workload (set by --workload): configuration name, shape, decoder
-WORKLOADS = {"paper": ("P2", 1), "fleet": ("S2", 1024)}   # name, default solves per step
+WORKLOADS = {"paper": ("P2", 1), "fleet": ("S2", 1024), "small": ("P1", 1)}   # name, default solves per step
 CFG = "P2"
 LAYERS = (67, 256, 256, 256, 1)
 K_, T_, G_ = 4096, 50, 4
