@@ -195,7 +195,7 @@ __host__ __device__ FusedLds fused_lds(int Tm, int Gm, int max_tiles, int feat_k
   L.base = take(sizeof(float) * 3 * Gm * (Tm + 1));
   L.los = take(sizeof(float) * 2 * Tm);
   L.dp = take(sizeof(float) * 3 * kTileR * (Tm + 1));
-  L.field = take(sizeof(float) * kTileR * Tm);
+  L.field = take(sizeof(float) * (kTileR * Tm + 1));   // + the reduction's sink entry
   L.fac = take(sizeof(double) * max_tiles);
   // positional encoding: three slots of the FP16 feature table
   L.feat = take(pe_slot_bytes(feat_ks) * 3);
@@ -378,23 +378,45 @@ __device__ __forceinline__ EdgeConsts edge_consts(const SolveDesc& d, int lane, 
   return e;
 }
 
-// Gate-frame point of this lane's row of block c (lanes 0 .. kRows-1).
-__device__ __forceinline__ void chunk_point(const Views& V, const EdgeConsts& e, int c, float* out4) {
-  const int q = c * e.Pc + e.p;
-  float px = 0.0f, py = 0.0f, pz = 0.0f;
-  if (e.p < e.Pc && q < e.npos) {
+// Gate-frame point of the row of block c that EdgeConsts e was made for, in
+// two parts (the LDS reads, then the arithmetic and the store) so that a wave
+// can issue the reads before other work and finish after it.  Branch-free:
+// a padding row or a position past the tile reads position 0 and stores the
+// zero point, so every lane of a wave may run it (lanes with the same row
+// store the same value).
+struct PointJob {
+  float dp[3], r[9], b[3];
+  bool ok;
+  int gate;
+  __device__ __forceinline__ void load(const Views& V, const EdgeConsts& e, int c) {
+    const int q = c * e.Pc + e.p;
+    ok = e.p < e.Pc && q < e.npos;
+    gate = e.p < e.Pc ? e.g : 0;
+    const int qv = ok ? q : 0;
     // q = kl T + t; (q + 1/2) / T is at least 1/(2T) away from an integer,
     // far more than the float error for q < 2^11
-    const int kl = (int)(((float)q + 0.5f) * e.invT), t = q - kl * e.T;
+    const int kl = (int)(((float)qv + 0.5f) * e.invT), t = qv - kl * e.T;
     const int tp = t + e.qoff;
     const float* dpp = V.dp + 3 * (kl * (e.T + 1) + tp);
     const float* R = V.rt + 9 * e.g;
-    const float* b = V.base + 3 * (e.g * (e.T + 1) + tp);
-    px = fmaf(R[0], dpp[0], fmaf(R[1], dpp[1], fmaf(R[2], dpp[2], b[0])));
-    py = fmaf(R[3], dpp[0], fmaf(R[4], dpp[1], fmaf(R[5], dpp[2], b[1])));
-    pz = fmaf(R[6], dpp[0], fmaf(R[7], dpp[1], fmaf(R[8], dpp[2], b[2])));
+    const float* bb = V.base + 3 * (e.g * (e.T + 1) + tp);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) { dp[i] = dpp[i]; b[i] = bb[i]; }
+#pragma unroll
+    for (int i = 0; i < 9; ++i) r[i] = R[i];
   }
-  *(float4*)out4 = make_float4(px, py, pz, (float)((e.p < e.Pc) ? e.g : 0));
+  __device__ __forceinline__ void store(float* out4) const {
+    const float px = fmaf(r[0], dp[0], fmaf(r[1], dp[1], fmaf(r[2], dp[2], b[0])));
+    const float py = fmaf(r[3], dp[0], fmaf(r[4], dp[1], fmaf(r[5], dp[2], b[1])));
+    const float pz = fmaf(r[6], dp[0], fmaf(r[7], dp[1], fmaf(r[8], dp[2], b[2])));
+    *(float4*)out4 = ok ? make_float4(px, py, pz, (float)gate) : make_float4(0.0f, 0.0f, 0.0f, (float)gate);
+  }
+};
+
+__device__ __forceinline__ void chunk_point(const Views& V, const EdgeConsts& e, int c, float* out4) {
+  PointJob j;
+  j.load(V, e, c);
+  j.store(out4);
 }
 
 // Coordinate comp of the gate-frame point of row r of block c, in the same
@@ -451,28 +473,52 @@ __device__ __forceinline__ void pe_block(const Views& V, const EdgeConsts& e, in
   }
 }
 
-// Output of this lane's row of block c (lanes 0 .. kRows-1 of one wave): sum
-// of the per-lane partials of the last layer's owners, max over each
-// position's gates into the tile's field table (the hinge is taken in the
-// tile epilogue).
-template <int WPL>
-__device__ __forceinline__ void chunk_reduce(const Views& V, const EdgeConsts& e, const float* opart, int c, int row) {
-  float acc = 0.0f;
-#pragma unroll
-  for (int w = 0; w < WPL; ++w) {
-    const float4 o = *(const float4*)(opart + 4 * (w * kRows + row));
-    acc += (o.x + o.y) + (o.z + o.w);
-  }
-  const float sv = acc + e.bout;
-  const int base = e.p * e.G;
-  float best = sv;
-  for (int g = 1; g < e.G; ++g) {
-    const float o = __shfl(sv, base + g, 64);
-    if (base + g < kRows) best = fmaxf(best, o);
-  }
-  const int q = c * e.Pc + e.p;
-  if (e.g == 0 && e.p < e.Pc && q < e.npos) V.field[q] = best;
+// Value of lane perm(lane) under a DPP lane pattern (quad permutation or row
+// mirror), every lane active.
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
 }
+
+// Output of one row of block c: sum of the per-lane partials of the last
+// layer's owners, max over each position's gates into the tile's field table
+// (the hinge is taken in the tile epilogue).  Like PointJob in two parts and
+// branch-free over the lanes (row = lane % 16, every 16-lane row of the wave
+// a copy): a store that has no position (a block outside 0 .. nblk-1, a
+// padding row, a gate other than the first) goes to the sink entry
+// field[kTileR T], which no position uses.
+template <int WPL>
+struct ReduceJob {
+  float4 o[WPL];
+  __device__ __forceinline__ void load(const float* opart, int row) {
+#pragma unroll
+    for (int w = 0; w < WPL; ++w) o[w] = *(const float4*)(opart + 4 * (w * kRows + row));
+  }
+  __device__ __forceinline__ void store(const Views& V, const EdgeConsts& e, int c, int nblk) const {
+    float acc = 0.0f;
+#pragma unroll
+    for (int w = 0; w < WPL; ++w) acc += (o[w].x + o[w].y) + (o[w].z + o[w].w);
+    const float sv = acc + e.bout;
+    float best = sv;
+    if ((e.G & (e.G - 1)) == 0) {
+      // G = 1, 2, 4, 8: a position's rows are an aligned group of G lanes;
+      // maximum by lane exchanges inside the group (xor 1, xor 2 in a quad,
+      // then the mirror of an 8-lane half row)
+      if (e.G >= 2) best = fmaxf(best, dpp_f32<0xB1>(best));
+      if (e.G >= 4) best = fmaxf(best, dpp_f32<0x4E>(best));
+      if (e.G >= 8) best = fmaxf(best, dpp_f32<0x141>(best));
+    } else {
+      const int base = e.p * e.G + (__lane_id() & ~(kRows - 1));
+      for (int g = 1; g < e.G; ++g) {
+        const float x = __shfl(sv, base + g, 64);
+        if (e.p * e.G + g < kRows) best = fmaxf(best, x);
+      }
+    }
+    const int q = c * e.Pc + e.p;
+    const bool ok = c >= 0 && c < nblk && e.g == 0 && e.p < e.Pc && q < e.npos;
+    V.field[ok ? q : kTileR * e.T] = best;
+  }
+};
 
 // Clipped control samples of the tile (Section IV-A) into V.samp.
 __device__ __forceinline__ void tile_noise(const Views& V, const SolveDesc& d, int k0, int Re, uint32_t tick) {
@@ -767,18 +813,47 @@ __device__ __forceinline__ void layer1_products(const float* pts, const char* fs
   }
 }
 
+// Edge work that a vector-first wave carries inside its vector phase: the
+// LDS reads are issued before the softplus of the owned layer and the result
+// stored after it, so that the read latency hides behind the vector work.
+struct NoEdge {
+  __device__ __forceinline__ void load() {}
+  __device__ __forceinline__ void store() const {}
+};
+struct PointEdge {      // gate-frame points of block c into slot `out`
+  const Views& V;
+  const EdgeConsts& e;
+  int c;
+  float* out;
+  PointJob j;
+  __device__ __forceinline__ void load() { j.load(V, e, c); }
+  __device__ __forceinline__ void store() const { j.store(out + 4 * (__lane_id() & (kRows - 1))); }
+};
+template <int WPL>
+struct ReduceEdge {     // output reduction of block c from the partials `opart`
+  const Views& V;
+  const EdgeConsts& e;
+  const float* opart;
+  int c, nblk;
+  ReduceJob<WPL> j;
+  __device__ __forceinline__ void load() { j.load(opart, __lane_id() & (kRows - 1)); }
+  __device__ __forceinline__ void store() const { j.store(V, e, c, nblk); }
+};
+
 // Vector part of a step: the epilogue of the owned layer from acc (softplus,
 // then the next layer's operand in `out`, or for the last layer this lane's
 // share of the output dot in `opart`), and softplus and operand of the
 // wave's NB layer-1 blocks x (first block b0) into `l1out`.
-template <int P, int H, int NHH, int OWN, int MB, int NB>
+template <int P, int H, int NHH, int OWN, int MB, int NB, class EG>
 __device__ __forceinline__ void vector_work(const f32x4 (&acc)[MB], const f32x4 (&x)[NB > 0 ? NB : 1], char* out,
                                             char* l1out, float* opart, const float* hb, const float* wo,
-                                            const DeviceWeights& w, int b0, int gw, int h, int nl, float scale_own) {
+                                            const DeviceWeights& w, int b0, int gw, int h, int nl, float scale_own,
+                                            EG& edge) {
   using PT = PrecTraits<P>;
   const int e0 = 16 * gw * MB + 4 * h;          // first owned neuron of this lane
   const uint32_t eoff = act_off<P, H>(nl, e0);
   float op = 0.0f;
+  edge.load();
 #pragma unroll
   for (int mb = 0; mb < MB; ++mb) {
     float xs[4], v[4];
@@ -794,6 +869,7 @@ __device__ __forceinline__ void vector_work(const f32x4 (&acc)[MB], const f32x4 
     }
     if (mb & 1) sched_fence();
   }
+  edge.store();
   if constexpr (OWN + 1 == NHH) opart[(gw * kRows + nl) * 4 + h] = op;
   const uint32_t loff = act_off<P, H>(nl, 16 * b0 + 4 * h);
 #pragma unroll
@@ -815,12 +891,13 @@ __device__ __forceinline__ void vector_work(const f32x4 (&acc)[MB], const f32x4 
 // the two parts in opposite order (MFIRST: products first), so that one
 // wave's matrix-core work runs beside the other's vector work.  Blocks outside
 // the tile's range run on stale data whose results are never read.
-template <int P, int H, int NHH, int OWN, int PAR, bool MFIRST, int MB, bool PE>
+template <int P, int H, int NHH, int OWN, int PAR, bool MFIRST, int MB, bool PE, class EG>
 __device__ __forceinline__ void pipeline_step(const Views& V, const DeviceWeights& w, int wave, int gw, int h,
                                               int nl, float scale_own, const FragT<P> (&wreg)[MB][H / 32],
                                               f32x4 (&acc)[2][MB], const float* pts_prev, const float* pts_cur,
                                               const char* fs_prev, const char* fs_cur,
-                                              f32x4 (&x1c)[L1Split<P, H>::A > 0 ? L1Split<P, H>::A : 1]) {
+                                              f32x4 (&x1c)[L1Split<P, H>::A > 0 ? L1Split<P, H>::A : 1],
+                                              EG& edge) {
   constexpr int WPL = kWaves / NHH;
   constexpr size_t AB = act_buf_bytes<P, H>();
   const char* in = V.act + (2 * OWN + PAR) * AB;
@@ -839,7 +916,7 @@ __device__ __forceinline__ void pipeline_step(const Views& V, const DeviceWeight
     products<P, H, OWN, MB>(in, boff, V.hb, gw, h, wreg, b0, acc[PAR]);
     layer1_products<H, NB, PE>(pts_prev, fs_prev, V.cf, V.w1p, l1b, h, nl, x1, w);
     sched_fence();
-    vector_work<P, H, NHH, OWN, MB, NB>(acc[1 - PAR], x1, out, l1out, op, V.hb, V.wo, w, l1b, gw, h, nl, scale_own);
+    vector_work<P, H, NHH, OWN, MB, NB>(acc[1 - PAR], x1, out, l1out, op, V.hb, V.wo, w, l1b, gw, h, nl, scale_own, edge);
   } else {
     // vector phase (layer-1 products of block s-1 carried from the previous
     // step), then the matrix-core phase, which ends with the layer-1
@@ -847,7 +924,8 @@ __device__ __forceinline__ void pipeline_step(const Views& V, const DeviceWeight
     // the vector phase, where it would queue behind the other wave's products
     constexpr int NB = L1Split<P, H>::A;
     read_operands<P, H>(in, boff, 0, b0);
-    vector_work<P, H, NHH, OWN, MB, NB>(acc[1 - PAR], x1c, out, l1out, op, V.hb, V.wo, w, l1b, gw, h, nl, scale_own);
+    vector_work<P, H, NHH, OWN, MB, NB>(acc[1 - PAR], x1c, out, l1out, op, V.hb, V.wo, w, l1b, gw, h, nl, scale_own,
+                                        edge);
     sched_fence();
     products<P, H, OWN, MB>(in, boff, V.hb, gw, h, wreg, b0, acc[PAR]);
     layer1_products<H, NB, PE>(pts_cur, fs_cur, V.cf, V.w1p, l1b, h, nl, x1c, w);
@@ -857,7 +935,7 @@ __device__ __forceinline__ void pipeline_step(const Views& V, const DeviceWeight
 // The decoder over one tile's blocks for a wave that owns hidden layer OWN.
 // Activation buffer (l, p) is the input of hidden layer l for blocks of
 // parity p.  Every wave runs the same number of steps and barriers.
-template <int P, int H, int NHH, int OWN, bool MFIRST, int MB, bool PE>
+template <int P, int H, int NHH, int OWN, bool MFIRST, int MB, bool PE, int EDGE>
 __device__ __forceinline__ void decoder_tile(const Views& V, const SolveDesc& d, const DeviceWeights& w, int wave,
                                              int lane, int gw, int h, int nl, float scale_own,
                                              const FragT<P> (&wreg)[MB][H / 32], int npos, int nblk) {
@@ -872,25 +950,34 @@ __device__ __forceinline__ void decoder_tile(const Views& V, const SolveDesc& d,
   f32x4 x1c[L1Split<P, H>::A > 0 ? L1Split<P, H>::A : 1];
 #pragma unroll
   for (int j = 0; j < (L1Split<P, H>::A > 0 ? L1Split<P, H>::A : 1); ++j) x1c[j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-  // Gate-frame points of block b live in slot b % 3: in step s wave 1 writes
-  // block s+1 while the layer-1 products read blocks s-1 and s.  The edge
-  // work goes to two waves that run their vector work first and have slack at
-  // the barrier (the products-first waves do not).
+  // Gate-frame points of block b live in slot b % 3: in step s one wave
+  // (EDGE 1) writes block s+1 while the layer-1 products read blocks s-1 and
+  // s, and another (EDGE 2) reduces the output of block s - lag.  Both are
+  // vector-first waves on different SIMDs, which finish their own work
+  // earliest; they run the edge work inside their vector phase.
   // With the positional encoding every thread also forms its share of the
   // features of block s+1 in step s, into feature slot (s+1) % 3.
-  const EdgeConsts ec = edge_consts(d, lane, npos, w.bout);
+  const EdgeConsts ec = edge_consts(d, lane & (kRows - 1), npos, w.bout);
   const size_t fslot = pe_slot_bytes(w.feat_k32);
-  if (wave == 1 && lane < kRows) chunk_point(V, ec, 0, V.pts + 4 * lane);
+  if (EDGE == 1 && lane < kRows) chunk_point(V, ec, 0, V.pts + 4 * lane);
   if constexpr (PE) pe_block(V, ec, 0, V.feat, w.pe_freqs, w.feat_k32, 64 * wave + lane);
   __syncthreads();
   int slot = 0;                       // = s % 3
-  auto edges = [&](int st, int par) {
-    const int nxt = slot == 2 ? 0 : slot + 1;
-    if (wave == 1 && lane < kRows) chunk_point(V, ec, st + 1, V.pts + 4 * (nxt * kRows + lane));
-    if constexpr (PE) pe_block(V, ec, st + 1, V.feat + nxt * fslot, w.pe_freqs, w.feat_k32, 64 * wave + lane);
-    const int br = st - lag;
-    if (wave == 2 && lane < kRows && br >= 0 && br < nblk)
-      chunk_reduce<WPL>(V, ec, V.opart + par * WPL * kRows * 4, br, lane);
+  auto edges = [&](int st) {
+    if constexpr (PE) {
+      const int nxt = slot == 2 ? 0 : slot + 1;
+      pe_block(V, ec, st + 1, V.feat + nxt * fslot, w.pe_freqs, w.feat_k32, 64 * wave + lane);
+    }
+  };
+  auto edge_job = [&](int st, int par) {
+    if constexpr (EDGE == 1) {
+      const int nxt = slot == 2 ? 0 : slot + 1;
+      return PointEdge{V, ec, st + 1, V.pts + 4 * kRows * nxt, {}};
+    } else if constexpr (EDGE == 2) {
+      return ReduceEdge<WPL>{V, ec, V.opart + par * WPL * kRows * 4, st - lag, nblk, {}};
+    } else {
+      return NoEdge{};
+    }
   };
   auto slot_pts = [&](int sl) { return V.pts + 4 * kRows * sl; };
   auto slot_fs = [&](int sl) { return V.feat + fslot * sl; };
@@ -900,17 +987,23 @@ __device__ __forceinline__ void decoder_tile(const Views& V, const SolveDesc& d,
     // instead of keeping a dozen of them live across the loop
     int hv = h, nv = nl;
     asm volatile("" : "+v"(hv), "+v"(nv));
-    edges(s, 0);
-    pipeline_step<P, H, NHH, OWN, 0, MFIRST, MB, PE>(V, w, wave, gw, hv, nv, scale_own, wreg, acc,
-                                                 slot_pts(slot == 0 ? 2 : slot - 1), slot_pts(slot),
-                                                 slot_fs(slot == 0 ? 2 : slot - 1), slot_fs(slot), x1c);
+    edges(s);
+    {
+      auto ej = edge_job(s, 0);
+      pipeline_step<P, H, NHH, OWN, 0, MFIRST, MB, PE>(V, w, wave, gw, hv, nv, scale_own, wreg, acc,
+                                                   slot_pts(slot == 0 ? 2 : slot - 1), slot_pts(slot),
+                                                   slot_fs(slot == 0 ? 2 : slot - 1), slot_fs(slot), x1c, ej);
+    }
     __syncthreads();
     slot = slot == 2 ? 0 : slot + 1;
     asm volatile("" : "+v"(hv), "+v"(nv));
-    edges(s + 1, 1);
-    pipeline_step<P, H, NHH, OWN, 1, MFIRST, MB, PE>(V, w, wave, gw, hv, nv, scale_own, wreg, acc,
-                                                 slot_pts(slot == 0 ? 2 : slot - 1), slot_pts(slot),
-                                                 slot_fs(slot == 0 ? 2 : slot - 1), slot_fs(slot), x1c);
+    edges(s + 1);
+    {
+      auto ej = edge_job(s + 1, 1);
+      pipeline_step<P, H, NHH, OWN, 1, MFIRST, MB, PE>(V, w, wave, gw, hv, nv, scale_own, wreg, acc,
+                                                   slot_pts(slot == 0 ? 2 : slot - 1), slot_pts(slot),
+                                                   slot_fs(slot == 0 ? 2 : slot - 1), slot_fs(slot), x1c, ej);
+    }
     __syncthreads();
     slot = slot == 2 ? 0 : slot + 1;
   }
@@ -967,15 +1060,15 @@ __global__ __launch_bounds__(kThreads, 1) void k_fused(FusedBatch batch, DeviceW
     // waves w and w + 4 share a SIMD: the second runs its products first
     // (with two hidden layers that is the owner of the last one, whose
     // epilogue needs the fewest registers beside two accumulator sets)
-    const bool mfirst = wave >= kWaves / 2;
-    if (NHH == 1) {
-      if (mfirst) decoder_tile<P, H, NHH, 0, true, MB, PE>(V, d, w, wave, lane, gw, h, nl, scale_own, wreg, npos, nblk);
-      else decoder_tile<P, H, NHH, 0, false, MB, PE>(V, d, w, wave, lane, gw, h, nl, scale_own, wreg, npos, nblk);
-    } else if (own == 0) {
-      decoder_tile<P, H, NHH, 0, false, MB, PE>(V, d, w, wave, lane, gw, h, nl, scale_own, wreg, npos, nblk);
-    } else {
-      decoder_tile<P, H, NHH, NHH - 1, true, MB, PE>(V, d, w, wave, lane, gw, h, nl, scale_own, wreg, npos, nblk);
-    }
+    // (waves 0 and kWaves / 2 - 1, vector first, also carry the edge work)
+    if (wave >= kWaves / 2)
+      decoder_tile<P, H, NHH, NHH - 1, true, MB, PE, 0>(V, d, w, wave, lane, gw, h, nl, scale_own, wreg, npos, nblk);
+    else if (wave == 0)
+      decoder_tile<P, H, NHH, 0, false, MB, PE, 1>(V, d, w, wave, lane, gw, h, nl, scale_own, wreg, npos, nblk);
+    else if (wave == kWaves / 2 - 1)
+      decoder_tile<P, H, NHH, 0, false, MB, PE, 2>(V, d, w, wave, lane, gw, h, nl, scale_own, wreg, npos, nblk);
+    else
+      decoder_tile<P, H, NHH, 0, false, MB, PE, 0>(V, d, w, wave, lane, gw, h, nl, scale_own, wreg, npos, nblk);
     tile_epilogue(V, d, k0, Re, tick);
   }
 }
