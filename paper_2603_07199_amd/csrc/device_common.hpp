@@ -11,6 +11,7 @@
 #include <stdint.h>
 
 #include "solve_desc.hpp"
+#include "weights.hpp"
 
 namespace mppi {
 
@@ -69,6 +70,30 @@ __device__ __forceinline__ void sample_control(const SolveDesc& d, uint32_t k, u
   }
 }
 
+// ---------------------------------------------------------------- latent fold
+// c_g = W1[:, 3:] z_g + b1 for gate g of solve d, in FP64 and rounded once:
+// the decoder's first layer applied to the latent block of its input [p; z]
+// (Section III-B), shared by all queries of a gate.  With an instance cache
+// (object permanence, Section IV-B-3) an observed gate's fold is also stored
+// there, and an unobserved gate's fold is taken from it.  One workgroup per
+// gate (any size).
+__device__ __forceinline__ void fold_gate(const SolveDesc& d, int g, const DeviceWeights& w) {
+  if (g >= d.G || d.sdf_kind != 0) return;
+  float* cache = d.cf_cache ? d.cf_cache + (size_t)g * d.H : nullptr;
+  if ((d.fold_cached >> g) & 1u) {
+    for (int m = threadIdx.x; m < d.H; m += blockDim.x) d.cfold[g * d.H + m] = cache[m];
+    return;
+  }
+  const float* z = d.z + g * kLatent;
+  for (int m = threadIdx.x; m < d.H; m += blockDim.x) {
+    // (the transposed block: neighbouring threads read neighbouring words)
+    double acc = w.b0[m];
+    for (int j = 0; j < kLatent; ++j) acc = fma(w.w0lat[(size_t)j * d.H + m], (double)z[j], acc);
+    d.cfold[g * d.H + m] = (float)acc;
+    if (cache) cache[m] = (float)acc;
+  }
+}
+
 // ---------------------------------------------------------------- dynamics
 // Rollout state in the local frame: dp is the position minus p0 + v0 t dt
 // (deviation from the initial ballistic drift), dv = v - v0, q attitude.
@@ -76,14 +101,54 @@ struct RolloutState {
   float dp[3], dv[3], q[4];
 };
 
-__device__ __forceinline__ void quad_step(RolloutState& s, const float u[4], float dt, float inv_m,
-                                          float g) {
+// Attitude increment of one step from the body rate (u[1], u[2], u[3]):
+// r = [cos(|w| dt/2), sin(|w| dt/2) w/|w|].  It depends on the input only,
+// so a rollout loop may form it ahead of the state update.  Two parts: the
+// Taylor series in (|w| dt/2)^2 for every lane (branch-free, truncation
+// < 3e-13 below 1/4: no division, no range reduction), then sincos for the
+// lanes at or above 1/4.
+__device__ __forceinline__ float quad_rotation_series(const float u[4], float dt, float r[4]) {
+  const float wx = u[1], wy = u[2], wz = u[3];
+  const float nrm = sqrtf(wx * wx + wy * wy + wz * wz);
+  const float half = 0.5f * nrm * dt;
+  const float x2 = half * half;
+  const float ch = fmaf(x2, fmaf(x2, fmaf(x2, fmaf(x2, 1.0f / 40320.0f, -1.0f / 720.0f), 1.0f / 24.0f), -0.5f), 1.0f);
+  const float so = 0.5f * dt *
+      fmaf(x2, fmaf(x2, fmaf(x2, fmaf(x2, 1.0f / 362880.0f, -1.0f / 5040.0f), 1.0f / 120.0f), -1.0f / 6.0f), 1.0f);
+  r[0] = ch;
+  r[1] = so * wx;
+  r[2] = so * wy;
+  r[3] = so * wz;
+  return half;
+}
+__device__ __forceinline__ void quad_rotation_large(const float u[4], float half, float r[4]) {
+  if (half >= 0.25f) {
+    const float wx = u[1], wy = u[2], wz = u[3];
+    const float nrm = sqrtf(wx * wx + wy * wy + wz * wz);
+    float sh, ch;
+    sincosf(half, &sh, &ch);
+    const float so = sh / nrm;
+    r[0] = ch;
+    r[1] = so * wx;
+    r[2] = so * wy;
+    r[3] = so * wz;
+  }
+}
+__device__ __forceinline__ void quad_rotation(const float u[4], float dt, float r[4]) {
+  quad_rotation_large(u, quad_rotation_series(u, dt, r), r);
+}
+
+// One step of the state with collective thrust f_c = u0 and the attitude
+// increment r of quad_rotation: position and velocity from the thrust along
+// the body z axis and gravity, then q <- q (x) r.
+__device__ __forceinline__ void quad_advance(RolloutState& s, float u0, const float r[4], float dt, float inv_m,
+                                             float g) {
   const float w = s.q[0], x = s.q[1], y = s.q[2], z = s.q[3];
   // R(q) e3: body z axis in the world frame.
   const float bx = 2.0f * (x * z + w * y);
   const float by = 2.0f * (y * z - w * x);
   const float bz = 1.0f - 2.0f * (x * x + y * y);
-  const float f = u[0] * inv_m;
+  const float f = u0 * inv_m;
   const float a[3] = {f * bx, f * by, fmaf(f, bz, -g)};
   const float hdt2 = 0.5f * dt * dt;
 #pragma unroll
@@ -91,28 +156,18 @@ __device__ __forceinline__ void quad_step(RolloutState& s, const float u[4], flo
     s.dp[i] = fmaf(a[i], hdt2, fmaf(s.dv[i], dt, s.dp[i]));
     s.dv[i] = fmaf(a[i], dt, s.dv[i]);
   }
-  // q <- q (x) [cos(|w| dt/2), sin(|w| dt/2) w/|w|]
-  const float wx = u[1], wy = u[2], wz = u[3];
-  const float nrm = sqrtf(wx * wx + wy * wy + wz * wz);
-  const float half = 0.5f * nrm * dt;
-  float so, ch;
-  if (half < 0.25f) {
-    // Taylor series in half^2 (truncation < 3e-13): cos(half) and
-    // sin(half) / nrm = dt/2 sinc(half), no division, no range reduction
-    const float x2 = half * half;
-    ch = fmaf(x2, fmaf(x2, fmaf(x2, fmaf(x2, 1.0f / 40320.0f, -1.0f / 720.0f), 1.0f / 24.0f), -0.5f), 1.0f);
-    so = 0.5f * dt *
-         fmaf(x2, fmaf(x2, fmaf(x2, fmaf(x2, 1.0f / 362880.0f, -1.0f / 5040.0f), 1.0f / 120.0f), -1.0f / 6.0f), 1.0f);
-  } else {
-    float sh;
-    sincosf(half, &sh, &ch);
-    so = sh / nrm;
-  }
-  const float rw = ch, rx = so * wx, ry = so * wy, rz = so * wz;
+  const float rw = r[0], rx = r[1], ry = r[2], rz = r[3];
   s.q[0] = w * rw - x * rx - y * ry - z * rz;
   s.q[1] = w * rx + x * rw + y * rz - z * ry;
   s.q[2] = w * ry - x * rz + y * rw + z * rx;
   s.q[3] = w * rz + x * ry - y * rx + z * rw;
+}
+
+__device__ __forceinline__ void quad_step(RolloutState& s, const float u[4], float dt, float inv_m,
+                                          float g) {
+  float r[4];
+  quad_rotation(u, dt, r);
+  quad_advance(s, u[0], r, dt, inv_m, g);
 }
 
 // Rotor-thrust-rate input (Section IV-A): the four rotor thrusts and the

@@ -429,7 +429,7 @@ void pack_solve(mppi_engine* e, const mppi_request* r, Solve* s, const double Lo
     const bool observed = r->gates[g].z != nullptr;
     if (observed) {
       // this request's observation becomes the instance's cached gate g
-      // (its fold is stored by k_fold when the solve runs)
+      // (its fold is stored by the fold kernel when the solve runs)
       memcpy(ii.R[g], r->gates[g].R, sizeof(ii.R[g]));
       memcpy(ii.t[g], r->gates[g].t, sizeof(ii.t[g]));
       ii.seen |= 1u << g;
@@ -626,7 +626,6 @@ int launch_staged(mppi_engine* e, Staged& sg, hipStream_t st, hipEvent_t t0, hip
     return MPPI_OK;
   }
   Aux& a = sg.aux;
-  HIPCHK(e, launch_fold(a.descs, (int)sg.solves.size(), a.maxG, e->dw, st));
   FusedBatch fb{a.descs, a.tiles, a.n_tiles, a.counter};
   HIPCHK(e, launch_fused(fb, (int)sg.solves.size(), e->dw, a.maxT, a.maxG, a.maxTiles, st, t0, t1));
   return MPPI_OK;
@@ -735,7 +734,7 @@ int upload_weights(mppi_engine* e, const mppi_sdf_weights* w) {
   if (mlp) {
     for (int m = 0; m < H; ++m) {
       for (int i = 0; i < 3; ++i) w1p[m * 4 + i] = w->W[0][(size_t)m * (NF + D) + i];
-      for (int j = 0; j < D; ++j) w0lat[(size_t)m * D + j] = w->W[0][(size_t)m * (NF + D) + NF + j];
+      for (int j = 0; j < D; ++j) w0lat[(size_t)j * H + m] = w->W[0][(size_t)m * (NF + D) + NF + j];
       b0[m] = w->b[0][m];
     }
     // encoded-point columns as 16x16x4 operand fragments [mb][ks][lane]
@@ -1283,7 +1282,6 @@ int mppi_step_noalloc(mppi_engine* e, const mppi_request* r, mppi_result* out) {
     char* ab = base + s.lay.total;
     HIPCHK(e, hipMemcpyAsync(ab, aux_host, aux_bytes, hipMemcpyHostToDevice, st));
     const SolveDesc* dd = (const SolveDesc*)ab;
-    HIPCHK(e, launch_fold(dd, 1, G, e->dw, st));
     FusedBatch fb{dd, (const int2*)(ab + o_tiles), nt, (uint32_t*)(ab + o_cnt)};
     HIPCHK(e, launch_fused(fb, 1, e->dw, T, G, nt, st, nullptr, nullptr));
   } else {

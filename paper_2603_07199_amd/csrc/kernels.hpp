@@ -23,7 +23,8 @@ struct PlainShape {
 hipError_t launch_plain(const SolveDesc* dd, const PlainShape& shape, const DeviceWeights& w,
                         hipStream_t s, hipEvent_t sdf_begin, hipEvent_t sdf_end);
 
-// Latent fold c_g = W1[:, 3:] z_g + b1 for the gates of n_solves descriptors.
+// Latent fold c_g = W1[:, 3:] z_g + b1 for the gates of n_solves descriptors
+// (the plain path; the fused path folds in its prep kernel).
 hipError_t launch_fold(const SolveDesc* descs, int n_solves, int G_max, const DeviceWeights& w,
                        hipStream_t s);
 

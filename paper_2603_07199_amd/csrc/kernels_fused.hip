@@ -21,14 +21,15 @@
 // H/8 of its neurons; with two, waves 0-3 own H/4 neurons each of the first
 // and waves 4-7 of the second.  Blocks of 16 rows flow through a software
 // pipeline; in step s
-//   wave 1          gate-frame points of block s
-//   every wave      layer 1 of block s-1, H/8 neurons each (FP32 matrix-core
-//                   product with the point, then softplus)
+//   wave 0          gate-frame points of block s+1
+//   every wave      layer 1 of block s-1 or s, H/16 neuron blocks shared
+//                   between the waves (FP32 matrix-core product with the
+//                   point, then softplus)
 //   owners of l     matrix-core products of layer l on block s-2-2l into one
 //                   of two register accumulator sets, and the activation
 //                   epilogue (softplus, bf16 split / output dot) of block
 //                   s-3-2l from the other set
-//   wave 2          output sum and max over gates of block s-2-2L
+//   wave 3          output sum and max over gates of block s-2-2L
 //                   (L hidden H x H layers)
 // with one workgroup barrier per step.  A wave's products and its epilogue
 // work on different blocks, so the matrix cores and the vector units overlap
@@ -557,12 +558,41 @@ __device__ __forceinline__ void tile_dynamics(const Views& V, const SolveDesc& d
   float* dpk = V.dp + 3 * tid * (T + 1);
   dpk[0] = dpk[1] = dpk[2] = 0.0f;
   float Jc = 0.0f, Jv = 0.0f;
-  for (int t = 0; t < T; ++t) {
-    const float4 uu = *(const float4*)(V.samp + 4 * (tid * T + t));
-    const float u[4] = {uu.x, uu.y, uu.z, uu.w};
-    Jc = fmaf(u[0], u[0], fmaf(u[1], u[1], fmaf(u[2], u[2], fmaf(u[3], u[3], Jc))));
-    if (d.Q_vis != 0.0f) Jv += alignment_term(s.q, V.los[2 * t] - s.dp[0], V.los[2 * t + 1] - s.dp[1]);
-    if constexpr (ROTOR) {
+  const float4* su = (const float4*)(V.samp + 4 * tid * T);
+  if constexpr (!ROTOR) {
+    // The attitude increment of a step depends on its input only: form the
+    // next step's increment (and read its input) during this step, so that
+    // the serial chain per step is the state update alone.
+    float4 uu = su[0];
+    float r[4];
+    {
+      const float u0[4] = {uu.x, uu.y, uu.z, uu.w};
+      quad_rotation(u0, d.dt, r);
+    }
+    for (int t = 0; t < T; ++t) {
+      const float u[4] = {uu.x, uu.y, uu.z, uu.w};
+      const float rc[4] = {r[0], r[1], r[2], r[3]};
+      const RolloutState s0 = s;
+      // straight-line part: next input and the series of its increment
+      // beside this step's update (the last step re-reads its own input)
+      uu = su[t + 1 < T ? t + 1 : t];
+      const float un[4] = {uu.x, uu.y, uu.z, uu.w};
+      const float half = quad_rotation_series(un, d.dt, r);
+      Jc = fmaf(u[0], u[0], fmaf(u[1], u[1], fmaf(u[2], u[2], fmaf(u[3], u[3], Jc))));
+      quad_advance(s, u[0], rc, d.dt, d.inv_mass, d.gravity);
+      dpk[3 * (t + 1) + 0] = s.dp[0];
+      dpk[3 * (t + 1) + 1] = s.dp[1];
+      dpk[3 * (t + 1) + 2] = s.dp[2];
+      quad_rotation_large(un, half, r);
+      if (d.Q_vis != 0.0f) Jv += alignment_term(s0.q, V.los[2 * t] - s0.dp[0], V.los[2 * t + 1] - s0.dp[1]);
+    }
+  } else {
+    // rotor input: the body rate, and with it the increment, is state
+    for (int t = 0; t < T; ++t) {
+      const float4 uu = su[t];
+      const float u[4] = {uu.x, uu.y, uu.z, uu.w};
+      Jc = fmaf(u[0], u[0], fmaf(u[1], u[1], fmaf(u[2], u[2], fmaf(u[3], u[3], Jc))));
+      if (d.Q_vis != 0.0f) Jv += alignment_term(s.q, V.los[2 * t] - s.dp[0], V.los[2 * t + 1] - s.dp[1]);
       RotorState rs;
 #pragma unroll
       for (int i = 0; i < 4; ++i) rs.thr[i] = rsm[i];
@@ -575,12 +605,10 @@ __device__ __forceinline__ void tile_dynamics(const Views& V, const SolveDesc& d
 #pragma unroll
       for (int i = 0; i < 3; ++i) rsm[4 + i] = rs.w[i];
       quad_step(s, uc, d.dt, d.inv_mass, d.gravity);
-    } else {
-      quad_step(s, u, d.dt, d.inv_mass, d.gravity);
+      dpk[3 * (t + 1) + 0] = s.dp[0];
+      dpk[3 * (t + 1) + 1] = s.dp[1];
+      dpk[3 * (t + 1) + 2] = s.dp[2];
     }
-    dpk[3 * (t + 1) + 0] = s.dp[0];
-    dpk[3 * (t + 1) + 1] = s.dp[1];
-    dpk[3 * (t + 1) + 2] = s.dp[2];
   }
   const float Jg = s.dp[0] * s.dp[0] + s.dp[1] * s.dp[1] + s.dp[2] * s.dp[2] +
                    2.0f * (s.dp[0] * d.fprog[0] + s.dp[1] * d.fprog[1] + s.dp[2] * d.fprog[2]);
@@ -755,13 +783,22 @@ __device__ __forceinline__ void products(const char* in, uint32_t boff, const fl
 // two-hidden-layer decoder carry the costly operand splits of the first
 // hidden layer, so the products-first waves take 3 of every 4 layer-1
 // blocks; with one activation term (BF16, FP8) the split is one conversion
-// and the blocks are shared equally.
+// and the blocks are shared equally.  The two vector-first waves that carry
+// the edge work (waves 0 and 3) hand one block each to the other two.
 template <int P, int H> struct L1Split {
   static constexpr int B = (H >= 256 && PrecTraits<P>::splits > 1) ? 3 : H / 16 / kWaves;  // per products-first wave
   static constexpr int A = (H / 16 - (kWaves / 2) * B) / (kWaves / 2);
   static_assert(A >= 0 && (kWaves / 2) * (A + B) * 16 == H, "layer-1 split");
-  // first block of wave w (waves 4-7 products first, 0-3 vector first)
-  __device__ static int first(int wave) { return wave >= kWaves / 2 ? (wave - kWaves / 2) * B : (kWaves / 2) * B + wave * A; }
+  static constexpr int S = A >= 1 ? 1 : 0;
+  // blocks of a vector-first wave with (EDGE) or without edge work
+  static constexpr int vf(bool edge) { return edge ? A - S : A + S; }
+  // first block of wave w (waves 4-7 products first, 0-3 vector first; the
+  // vector-first counts are A - S, A + S, A + S, A - S)
+  __device__ static int first(int wave) {
+    return wave >= kWaves / 2 ? (wave - kWaves / 2) * B
+                              : (kWaves / 2) * B + wave * A + (wave == 1 ? -S : wave == 3 ? S : 0);
+  }
+  static_assert(kWaves == 8, "vector-first waves 0-3 with edge work on waves 0 and 3");
 };
 
 // PE (positional encoding, Section III-B): the point enters as PE(p), a
@@ -891,13 +928,12 @@ __device__ __forceinline__ void vector_work(const f32x4 (&acc)[MB], const f32x4 
 // the two parts in opposite order (MFIRST: products first), so that one
 // wave's matrix-core work runs beside the other's vector work.  Blocks outside
 // the tile's range run on stale data whose results are never read.
-template <int P, int H, int NHH, int OWN, int PAR, bool MFIRST, int MB, bool PE, class EG>
+template <int P, int H, int NHH, int OWN, int PAR, bool MFIRST, int MB, bool PE, int NBV, class EG>
 __device__ __forceinline__ void pipeline_step(const Views& V, const DeviceWeights& w, int wave, int gw, int h,
                                               int nl, float scale_own, const FragT<P> (&wreg)[MB][H / 32],
                                               f32x4 (&acc)[2][MB], const float* pts_prev, const float* pts_cur,
                                               const char* fs_prev, const char* fs_cur,
-                                              f32x4 (&x1c)[L1Split<P, H>::A > 0 ? L1Split<P, H>::A : 1],
-                                              EG& edge) {
+                                              f32x4 (&x1c)[NBV > 0 ? NBV : 1], EG& edge) {
   constexpr int WPL = kWaves / NHH;
   constexpr size_t AB = act_buf_bytes<P, H>();
   const char* in = V.act + (2 * OWN + PAR) * AB;
@@ -922,7 +958,7 @@ __device__ __forceinline__ void pipeline_step(const Views& V, const DeviceWeight
     // step), then the matrix-core phase, which ends with the layer-1
     // products of block s for the next step: no matrix-core instruction in
     // the vector phase, where it would queue behind the other wave's products
-    constexpr int NB = L1Split<P, H>::A;
+    constexpr int NB = NBV;
     read_operands<P, H>(in, boff, 0, b0);
     vector_work<P, H, NHH, OWN, MB, NB>(acc[1 - PAR], x1c, out, l1out, op, V.hb, V.wo, w, l1b, gw, h, nl, scale_own,
                                         edge);
@@ -947,9 +983,10 @@ __device__ __forceinline__ void decoder_tile(const Views& V, const SolveDesc& d,
   for (int p = 0; p < 2; ++p)
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb) acc[p][mb] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-  f32x4 x1c[L1Split<P, H>::A > 0 ? L1Split<P, H>::A : 1];
+  constexpr int NBV = L1Split<P, H>::vf(EDGE != 0);   // layer-1 blocks of a vector-first wave
+  f32x4 x1c[NBV > 0 ? NBV : 1];
 #pragma unroll
-  for (int j = 0; j < (L1Split<P, H>::A > 0 ? L1Split<P, H>::A : 1); ++j) x1c[j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  for (int j = 0; j < (NBV > 0 ? NBV : 1); ++j) x1c[j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
   // Gate-frame points of block b live in slot b % 3: in step s one wave
   // (EDGE 1) writes block s+1 while the layer-1 products read blocks s-1 and
   // s, and another (EDGE 2) reduces the output of block s - lag.  Both are
@@ -990,7 +1027,7 @@ __device__ __forceinline__ void decoder_tile(const Views& V, const SolveDesc& d,
     edges(s);
     {
       auto ej = edge_job(s, 0);
-      pipeline_step<P, H, NHH, OWN, 0, MFIRST, MB, PE>(V, w, wave, gw, hv, nv, scale_own, wreg, acc,
+      pipeline_step<P, H, NHH, OWN, 0, MFIRST, MB, PE, NBV>(V, w, wave, gw, hv, nv, scale_own, wreg, acc,
                                                    slot_pts(slot == 0 ? 2 : slot - 1), slot_pts(slot),
                                                    slot_fs(slot == 0 ? 2 : slot - 1), slot_fs(slot), x1c, ej);
     }
@@ -1000,7 +1037,7 @@ __device__ __forceinline__ void decoder_tile(const Views& V, const SolveDesc& d,
     edges(s + 1);
     {
       auto ej = edge_job(s + 1, 1);
-      pipeline_step<P, H, NHH, OWN, 1, MFIRST, MB, PE>(V, w, wave, gw, hv, nv, scale_own, wreg, acc,
+      pipeline_step<P, H, NHH, OWN, 1, MFIRST, MB, PE, NBV>(V, w, wave, gw, hv, nv, scale_own, wreg, acc,
                                                    slot_pts(slot == 0 ? 2 : slot - 1), slot_pts(slot),
                                                    slot_fs(slot == 0 ? 2 : slot - 1), slot_fs(slot), x1c, ej);
     }
@@ -1073,33 +1110,57 @@ __global__ __launch_bounds__(kThreads, 1) void k_fused(FusedBatch batch, DeviceW
   }
 }
 
-// Zero the batch's work counter.
-__global__ void k_fused_prep(FusedBatch b) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) *b.tile_counter = 0u;
+// Before the fused kernel: zero the batch's work counter and fold the
+// latent block of every gate of every solve (workgroup (g, solve)).
+__global__ __launch_bounds__(256) void k_fused_prep(FusedBatch b, DeviceWeights w) {
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *b.tile_counter = 0u;
+  fold_gate(b.descs[blockIdx.y], blockIdx.x, w);
 }
 
 constexpr int kMergeThreads = 1024;
-constexpr int kMergeChunks = 4;      // tile ranges of the U* sums
+constexpr int kMergeSlice = 32;      // U* entries per merge workgroup (at most)
 
-// Merge of one solve's tile partials (workgroup = solve; runs after the fused
-// kernel, whose completion makes every partial visible):
+// Merge workgroups of a solve: each takes a slice of the 4T entries of U*
+// (and of the K normalised weights).  A function of the solve alone, so the
+// summation order below never depends on the rest of the batch.
+__host__ __device__ constexpr int merge_groups(int T) { return (4 * T + kMergeSlice - 1) / kMergeSlice; }
+
+// Merge of one solve's tile partials (runs after the fused kernel, whose
+// completion makes every partial visible); workgroup (solve, c):
 //   rho = min_i rho_i, f_i = exp(-(rho_i - rho) / lambda),
 //   eta = sum_i eta_i f_i, U*[t][c] = sum_i S_i[t][c] f_i / eta,
-// then the normalised weights, the warm start, the tick and the scalars.
-// Every sum runs in an order fixed by the tile index (U*: kMergeChunks
-// consecutive tile ranges, each summed in order, then the ranges in order),
-// so the result does not depend on which workgroup ran which tile or on what
-// else was in the batch.
+// every workgroup forming rho, f and eta itself (the same values, in the same
+// order), then its slice of U* and of the normalised weights; workgroup 0
+// also the warm-start end, the tick and the scalars.  The U* sums run over
+// C consecutive tile ranges, each summed in tile order, then the ranges in
+// order, with C a function of T and the tile count only: the result does not
+// depend on which workgroup ran which tile or on what else was in the batch.
 __global__ __launch_bounds__(kMergeThreads) void k_fused_merge(FusedBatch batch) {
   extern __shared__ __align__(16) char lds[];
   constexpr int NW = kMergeThreads / 64;
   const SolveDesc& d = batch.descs[blockIdx.x];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int n = d.n_tiles, T = d.T, K = d.K;
+  const int ng = merge_groups(T), c = blockIdx.y;
+  if (c >= ng) return;
+  const int nU = 4 * T, L = (nU + ng - 1) / ng, u0 = c * L, u1 = min(nU, u0 + L);
+  const int C = max(1, min(n, kMergeThreads / L));    // tile ranges of the U* sums
   double* red = (double*)lds;          // 3 NW per-wave partial results
-  double* part = red + 3 * NW;         // kMergeChunks x 4T partial sums of U*
-  double* fac = part + kMergeChunks * 4 * T;   // n tile factors
-  const uint32_t tick = d.tick_fixed == 0xFFFFFFFFu ? *d.tick_slot : d.tick_fixed;
+  double* fac = red + 3 * NW;          // n tile factors
+  double* part = fac + n;              // C x L partial sums of the slice
+  // Reads that do not depend on rho go out first, so that their latency
+  // passes during the reductions: this thread's U* item (tile range rg,
+  // entry o; C L <= kMergeThreads, so at most one) up to kPre of its tiles,
+  // and the first of its costs for the weights.
+  constexpr int kPre = 16;
+  const int rg = tid / L, o = u0 + (tid - rg * L);
+  const int j0 = rg * n / C, j1 = tid < C * L ? (rg + 1) * n / C : j0;
+  const bool item = tid < C * L && o < u1;
+  double sv[kPre];
+#pragma unroll
+  for (int q = 0; q < kPre; ++q) sv[q] = (item && j0 + q < j1) ? d.partials[(size_t)(j0 + q) * kPartStride(T) + 4 + o] : 0.0;
+  const int kb = (int)((long)K * c / ng), ke = (int)((long)K * (c + 1) / ng);
+  const float J0 = (d.wn && kb + tid < ke) ? d.J[kb + tid] : 0.0f;
   // rho = min over tiles with weight (min is exact in any order)
   double r = INFINITY;
   for (int j = tid; j < n; j += kMergeThreads) {
@@ -1137,24 +1198,25 @@ __global__ __launch_bounds__(kMergeThreads) void k_fused_merge(FusedBatch batch)
   }
   const bool ok = isfinite(rho) && eta > 0.0;
   double* res = d.result;
-  // U*[t][c]: partial sums over kMergeChunks tile ranges, each in tile order
-  if (ok)
-    for (int i = tid; i < kMergeChunks * 4 * T; i += kMergeThreads) {
-      const int rg = i / (4 * T), o = i - rg * 4 * T;
-      const int j0 = rg * n / kMergeChunks, j1 = (rg + 1) * n / kMergeChunks;
-      double sacc = 0.0;
+  // the slice of U*: partial sums over C tile ranges, each in tile order
+  if (ok && tid < C * L) {
+    double sacc = 0.0;
+    if (item) {
+#pragma unroll
+      for (int q = 0; q < kPre; ++q)
+        if (j0 + q < j1) sacc = fma(sv[q], fac[j0 + q], sacc);
 #pragma unroll 8
-      for (int j = j0; j < j1; ++j) sacc = fma(d.partials[(size_t)j * kPartStride(T) + 4 + o], fac[j], sacc);
-      part[i] = sacc;
+      for (int j = j0 + kPre; j < j1; ++j) sacc = fma(d.partials[(size_t)j * kPartStride(T) + 4 + o], fac[j], sacc);
     }
+    part[tid] = sacc;
+  }
   __syncthreads();
-  for (int i = tid; i < 4 * T; i += kMergeThreads) {
+  for (int i = u0 + tid; i < u1; i += kMergeThreads) {
     const int t = i >> 2, ch = i & 3;
     double U;
     if (ok) {
-      double sacc = part[i];
-#pragma unroll
-      for (int rg = 1; rg < kMergeChunks; ++rg) sacc += part[rg * 4 * T + i];
+      double sacc = part[i - u0];
+      for (int rg = 1; rg < C; ++rg) sacc += part[rg * L + (i - u0)];
       U = sacc / eta;
     } else {
       const int tt = t < d.U_len ? t : d.U_len - 1;
@@ -1168,11 +1230,12 @@ __global__ __launch_bounds__(kMergeThreads) void k_fused_merge(FusedBatch batch)
     }
   }
   if (d.wn)
-    for (int k = tid; k < K; k += kMergeThreads) {
-      const float J = d.J[k];
+    for (int k = kb + tid; k < ke; k += kMergeThreads) {
+      const float J = k == kb + tid ? J0 : d.J[k];
       d.wn[k] = (ok && isfinite(J)) ? exp(-((double)J - rho) * d.inv_lambda) / eta : 0.0;
     }
-  if (tid == 0) {
+  if (c == 0 && tid == 0) {
+    const uint32_t tick = d.tick_fixed == 0xFFFFFFFFu ? *d.tick_slot : d.tick_fixed;
     double* rr = res + 4 * T;
     rr[RES_TICK] = (double)tick;
     if (ok) {
@@ -1654,7 +1717,7 @@ static hipError_t launch_fused_p(const FusedBatch& b, const DeviceWeights& w, in
 
 hipError_t launch_fused(const FusedBatch& b, int n_solves, const DeviceWeights& w, int max_T, int max_G,
                         int max_tiles, hipStream_t s, hipEvent_t begin, hipEvent_t end) {
-  hipLaunchKernelGGL(k_fused_prep, dim3(1), dim3(64), 0, s, b);
+  hipLaunchKernelGGL(k_fused_prep, dim3(max_G, n_solves), dim3(256), 0, s, b, w);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (begin && (e = hipEventRecord(begin, s)) != hipSuccess) return e;
@@ -1668,8 +1731,9 @@ hipError_t launch_fused(const FusedBatch& b, int n_solves, const DeviceWeights& 
   }
   if (e != hipSuccess) return e;
   if (end && (e = hipEventRecord(end, s)) != hipSuccess) return e;
-  const size_t merge_lds = sizeof(double) * (3 * (kMergeThreads / 64) + (size_t)kMergeChunks * 4 * max_T + (size_t)max_tiles);
-  hipLaunchKernelGGL(k_fused_merge, dim3(n_solves), dim3(kMergeThreads), merge_lds, s, b);
+  // per workgroup: the reductions, n tile factors, C x L <= kMergeThreads partial sums
+  const size_t merge_lds = sizeof(double) * (3 * (kMergeThreads / 64) + (size_t)max_tiles + kMergeThreads);
+  hipLaunchKernelGGL(k_fused_merge, dim3(n_solves, merge_groups(max_T)), dim3(kMergeThreads), merge_lds, s, b);
   return hipGetLastError();
 }
 

@@ -27,29 +27,8 @@ __device__ __forceinline__ uint32_t solve_tick(const SolveDesc& d) {
 }
 
 // ------------------------------------------------------------------ latent fold
-// c_g = W1[:, 3:] z_g + b1 for every gate of every solve in descs (grid.y),
-// in FP64 and rounded once: the decoder's first layer applied to the latent
-// block of its input [p; z] (Section III-B), shared by all queries of a gate.
-// With an instance cache (object permanence, Section IV-B-3) an observed
-// gate's fold is also stored there, and an unobserved gate's fold is taken
-// from it.
 __global__ __launch_bounds__(256) void k_fold(const SolveDesc* __restrict__ descs, DeviceWeights w) {
-  const SolveDesc& d = descs[blockIdx.y];
-  const int g = blockIdx.x;
-  if (g >= d.G || d.sdf_kind != 0) return;
-  float* cache = d.cf_cache ? d.cf_cache + (size_t)g * d.H : nullptr;
-  if ((d.fold_cached >> g) & 1u) {
-    for (int m = threadIdx.x; m < d.H; m += blockDim.x) d.cfold[g * d.H + m] = cache[m];
-    return;
-  }
-  const float* z = d.z + g * kLatent;
-  for (int m = threadIdx.x; m < d.H; m += blockDim.x) {
-    double acc = w.b0[m];
-    const double* wr = w.w0lat + (size_t)m * kLatent;
-    for (int j = 0; j < kLatent; ++j) acc = fma(wr[j], (double)z[j], acc);
-    d.cfold[g * d.H + m] = (float)acc;
-    if (cache) cache[m] = (float)acc;
-  }
+  fold_gate(descs[blockIdx.y], blockIdx.x, w);
 }
 
 hipError_t launch_fold(const SolveDesc* descs, int n_solves, int G_max, const DeviceWeights& w,

@@ -15,7 +15,7 @@ struct DeviceWeights {
   const float* w1p;      // H x 4: W1[:, 0..2], 0
   const float* hbias;    // (n_hidden - 1) x H
   const float* wout;     // H
-  const double* w0lat;   // H x 64: latent block of the first layer (float32 values)
+  const double* w0lat;   // 64 x H (transposed): latent block of the first layer (float32 values)
   const double* b0;      // H: first-layer bias
   float bout;
   // FP32: per hidden layer, fragments [mb][ks][64] of W[16 mb + lane%16][4 ks + lane/16]
