@@ -560,29 +560,29 @@ __device__ __forceinline__ void tile_dynamics(const Views& V, const SolveDesc& d
   float Jc = 0.0f, Jv = 0.0f;
   const float4* su = (const float4*)(V.samp + 4 * tid * T);
   if constexpr (!ROTOR) {
-    // The attitude increment of a step depends on its input only: form the
-    // next step's increment (and read its input) during this step, so that
-    // the serial chain per step is the state update alone.
-    float4 uu = su[0];
+    // The attitude increment of a step depends on its input only: the loop
+    // forms the next step's increment beside this step's update, and reads
+    // inputs two steps ahead, so that the serial chain per step is the state
+    // update alone.
+    float4 ua = su[0], ub = su[T > 1 ? 1 : 0];
     float r[4];
     {
-      const float u0[4] = {uu.x, uu.y, uu.z, uu.w};
+      const float u0[4] = {ua.x, ua.y, ua.z, ua.w};
       quad_rotation(u0, d.dt, r);
     }
     for (int t = 0; t < T; ++t) {
-      const float u[4] = {uu.x, uu.y, uu.z, uu.w};
+      const float u[4] = {ua.x, ua.y, ua.z, ua.w};
+      const float un[4] = {ub.x, ub.y, ub.z, ub.w};
       const float rc[4] = {r[0], r[1], r[2], r[3]};
       const RolloutState s0 = s;
-      // straight-line part: next input and the series of its increment
-      // beside this step's update (the last step re-reads its own input)
-      uu = su[t + 1 < T ? t + 1 : t];
-      const float un[4] = {uu.x, uu.y, uu.z, uu.w};
+      quad_advance(s, u[0], rc, d.dt, d.inv_mass, d.gravity);
       const float half = quad_rotation_series(un, d.dt, r);
       Jc = fmaf(u[0], u[0], fmaf(u[1], u[1], fmaf(u[2], u[2], fmaf(u[3], u[3], Jc))));
-      quad_advance(s, u[0], rc, d.dt, d.inv_mass, d.gravity);
       dpk[3 * (t + 1) + 0] = s.dp[0];
       dpk[3 * (t + 1) + 1] = s.dp[1];
       dpk[3 * (t + 1) + 2] = s.dp[2];
+      ua = ub;
+      ub = su[t + 2 < T ? t + 2 : T - 1];
       quad_rotation_large(un, half, r);
       if (d.Q_vis != 0.0f) Jv += alignment_term(s0.q, V.los[2 * t] - s0.dp[0], V.los[2 * t + 1] - s0.dp[1]);
     }
