@@ -615,6 +615,157 @@ __device__ __forceinline__ void tile_dynamics(const Views& V, const SolveDesc& d
   V.jl[tid] = d.Q_gate * Jg + d.R_u * Jc + d.Q_vis * Jv;
 }
 
+// Dynamics of the tile's rollouts by scans over the horizon, for the
+// collective-thrust + body-rate input, whose attitude increments depend on
+// the input only (Section IV-A model; the same per-step arithmetic as
+// quad_advance, summed in another order).  32 lanes per rollout (two
+// rollouts per wave), lane l taking steps l C .. l C + C - 1, C = ceil(T/32):
+//   attitude  q_t = q_0 (x) r_0 (x) ... (x) r_{t-1}: each lane multiplies its
+//             chunk's increments, an exclusive scan over the lanes gives the
+//             attitude at the chunk's start;
+//   velocity  dv_t = sum_{s<t} a_s dt, a_s = (u_s,0 / m) R(q_s) e3 - g e3;
+//   position  dp_t = sum_{s<t} (dv_s dt + a_s dt^2 / 2);
+// each from an exclusive scan of the lanes' chunk sums, then the chunk's own
+// steps in order.  Costs as in tile_dynamics.
+struct Quat {
+  float w, x, y, z;
+};
+__device__ __forceinline__ Quat qmul(const Quat& a, const Quat& b) {
+  return Quat{a.w * b.w - a.x * b.x - a.y * b.y - a.z * b.z, a.w * b.x + a.x * b.w + a.y * b.z - a.z * b.y,
+              a.w * b.y - a.x * b.z + a.y * b.w + a.z * b.x, a.w * b.z + a.x * b.y - a.y * b.x + a.z * b.w};
+}
+__device__ __forceinline__ float up32(float v, int dd) { return __shfl_up(v, (unsigned)dd, 32); }
+
+// Exclusive prefix sum over the 32 lanes of each half-wave.
+__device__ __forceinline__ float scan_excl32(float v, int l) {
+#pragma unroll
+  for (int dd = 1; dd < 32; dd <<= 1) {
+    const float o = up32(v, dd);
+    if (l >= dd) v += o;
+  }
+  const float e = up32(v, 1);
+  return l == 0 ? 0.0f : e;
+}
+
+__device__ void tile_dynamics_scan(const Views& V, const SolveDesc& d, int Re) {
+  const int tid = threadIdx.x, l = tid & 31, k = tid >> 5;
+  const int T = d.T, C = (T + 31) >> 5;   // C <= 4 (T <= kMaxT = 128)
+  const bool active = k < Re;
+  const int kk = active ? k : 0;          // idle halves compute rollout 0 and store nothing
+  const float4* su = (const float4*)(V.samp + 4 * kk * T);
+  const int t0 = l * C;
+  const float dt = d.dt, hdt2 = 0.5f * d.dt * d.dt, im = d.inv_mass, g = d.gravity;
+  // increments of the chunk and their product; |u|^2 of its steps
+  float r[4][4], f[4];
+  float jc = 0.0f;
+  Quat P{1.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int t = t0 + c;
+    if (c < C && t < T) {
+      const float4 uu = su[t];
+      const float u[4] = {uu.x, uu.y, uu.z, uu.w};
+      quad_rotation(u, dt, r[c]);
+      f[c] = u[0] * im;
+      jc = fmaf(u[0], u[0], fmaf(u[1], u[1], fmaf(u[2], u[2], fmaf(u[3], u[3], jc))));
+    } else {
+      r[c][0] = 1.0f;
+      r[c][1] = r[c][2] = r[c][3] = 0.0f;
+      f[c] = 0.0f;
+    }
+    P = qmul(P, Quat{r[c][0], r[c][1], r[c][2], r[c][3]});
+  }
+  // attitude at the chunk's start: q_0 (x) (exclusive product of the chunks before)
+#pragma unroll
+  for (int dd = 1; dd < 32; dd <<= 1) {
+    const Quat o{up32(P.w, dd), up32(P.x, dd), up32(P.y, dd), up32(P.z, dd)};
+    if (l >= dd) P = qmul(o, P);
+  }
+  Quat E{up32(P.w, 1), up32(P.x, 1), up32(P.y, 1), up32(P.z, 1)};
+  if (l == 0) E = Quat{1.0f, 0.0f, 0.0f, 0.0f};
+  const Quat qs = qmul(Quat{d.q0[0], d.q0[1], d.q0[2], d.q0[3]}, E);
+  // accelerations of the chunk's steps and their sum
+  float a[4][3], A[3] = {0.0f, 0.0f, 0.0f};
+  {
+    Quat q = qs;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const float bx = 2.0f * (q.x * q.z + q.w * q.y);
+      const float by = 2.0f * (q.y * q.z - q.w * q.x);
+      const float bz = 1.0f - 2.0f * (q.x * q.x + q.y * q.y);
+      const bool in = c < C && t0 + c < T;
+      a[c][0] = in ? f[c] * bx : 0.0f;
+      a[c][1] = in ? f[c] * by : 0.0f;
+      a[c][2] = in ? fmaf(f[c], bz, -g) : 0.0f;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) A[i] += a[c][i];
+      q = qmul(q, Quat{r[c][0], r[c][1], r[c][2], r[c][3]});
+    }
+  }
+  // velocity at the chunk's start, then the chunk's position increment
+  float dv0[3], D[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int i = 0; i < 3; ++i) dv0[i] = scan_excl32(A[i], l) * dt;
+  {
+    float dv[3] = {dv0[0], dv0[1], dv0[2]};
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      if (c < C && t0 + c < T)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          D[i] += fmaf(a[c][i], hdt2, dv[i] * dt);
+          dv[i] = fmaf(a[c][i], dt, dv[i]);
+        }
+  }
+  float dp[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) dp[i] = scan_excl32(D[i], l);
+  // the chunk's steps: positions out, alignment cost from the step-start state
+  float* dpk = V.dp + 3 * k * (T + 1);
+  if (active && l == 0) dpk[0] = dpk[1] = dpk[2] = 0.0f;
+  float jv = 0.0f;
+  {
+    Quat q = qs;
+    float dv[3] = {dv0[0], dv0[1], dv0[2]};
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int t = t0 + c;
+      if (c < C && t < T) {
+        if (d.Q_vis != 0.0f) {
+          const float qa[4] = {q.w, q.x, q.y, q.z};
+          jv += alignment_term(qa, V.los[2 * t] - dp[0], V.los[2 * t + 1] - dp[1]);
+        }
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          dp[i] = fmaf(a[c][i], hdt2, fmaf(dv[i], dt, dp[i]));
+          dv[i] = fmaf(a[c][i], dt, dv[i]);
+        }
+        if (active) {
+          dpk[3 * (t + 1) + 0] = dp[0];
+          dpk[3 * (t + 1) + 1] = dp[1];
+          dpk[3 * (t + 1) + 2] = dp[2];
+        }
+        q = qmul(q, Quat{r[c][0], r[c][1], r[c][2], r[c][3]});
+      }
+    }
+  }
+  // rollout sums over the 32 lanes (fixed butterfly) and the final position
+#pragma unroll
+  for (int m = 16; m >= 1; m >>= 1) {
+    jc += __shfl_xor(jc, m, 32);
+    jv += __shfl_xor(jv, m, 32);
+  }
+  const int ll = (T - 1) / C;              // lane holding the last step
+  float pT[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) pT[i] = __shfl(dp[i], ll, 32);
+  if (active && l == 0) {
+    const float Jg = pT[0] * pT[0] + pT[1] * pT[1] + pT[2] * pT[2] +
+                     2.0f * (pT[0] * d.fprog[0] + pT[1] * d.fprog[1] + pT[2] * d.fprog[2]);
+    V.jl[k] = d.Q_gate * Jg + d.R_u * jc + d.Q_vis * jv;
+  }
+}
+
 // Per-tile tables, noise and dynamics (all threads of the workgroup call it).
 // The folded latent rows go to V.cf with row stride H + cf_pad.
 __device__ void tile_prologue(const Views& V, const SolveDesc& d, int k0, int Re, uint32_t tick, int H,
@@ -627,10 +778,12 @@ __device__ void tile_prologue(const Views& V, const SolveDesc& d, int k0, int Re
     for (int i = tid; i < 2 * T; i += (int)blockDim.x) V.los[i] = d.los[i];
   tile_noise(V, d, k0, Re, tick);
   __syncthreads();
-  // dynamics: one lane per rollout
-  if (tid < Re) {
-    if (d.dyn == 1) tile_dynamics<true>(V, d, tid);
-    else tile_dynamics<false>(V, d, tid);
+  // dynamics: rotor input one lane per rollout, serial over the horizon
+  // (its body rate is state); collective thrust + body rate by scans
+  if (d.dyn == 1) {
+    if (tid < Re) tile_dynamics<true>(V, d, tid);
+  } else {
+    if (tid < 32 * kTileR) tile_dynamics_scan(V, d, Re);
   }
   __syncthreads();
 }
