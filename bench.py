@@ -161,6 +161,7 @@ def run_leg(M, path, precision, batch, steps, warmup):
         "sdf_ms": st["sdf_ms"] / max(st["sdf_launches"], 1),
         "sdf_launches": st["sdf_launches"],
         "solve_ms": st["solve_ms"] / max(st["solve_launches"], 1),
+        "wide_region": int(st["wide_region"]),
     }
 
 
@@ -410,7 +411,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": _workload_str(),
                    "path": args.path, "precision": args.precision, "solves_per_step": args.batch,
-                   "parallelism": "single-gpu"},
+                   "parallelism": "single-gpu",
+                   # H = 512: the weight-fragment read-ahead region tuned for this shape in warm-up
+                   **({"wide_region_tuned": main_leg["wide_region"]}
+                      if LAYERS[1] == 512 and args.path == "fused" else {})},
         "latency_ms": {"p50": float(np.percentile(main_leg["lat_ms"], 50)),
                        "p99": float(np.percentile(main_leg["lat_ms"], 99))},
         "roofline_valu": {"bound": "alu",

@@ -130,6 +130,16 @@ typedef struct mppi_config {
    * oldest admissible request.  Bounds how long a request waits behind a
    * burst.  0 = the default, 2^21 query points. */
   uint64_t wave_queries_max;
+  /* Fused path, H = 512 (weights streamed through LDS): neuron blocks per
+   * scheduling region of a K-step, i.e. how far ahead a wave reads its weight
+   * fragments: 2, 4 or 8, or 0 = tuned: the first launch of each shape
+   * (precision, H, max G, max T of the launch) times the three on that
+   * launch's first tiles (two per compute unit, synchronously) and keeps the
+   * fastest for the engine's life.  Every choice gives the same results bit
+   * for bit (only the order of independent products changes).  Other values:
+   * EINVAL.  mppi_step_noalloc never tunes: it takes a shape's tuned choice
+   * if there is one, else 4. */
+  int32_t wide_region;
 } mppi_config;
 
 /* Decoder weights, row-major float32 as a (n_out x n_in) matrix per layer
@@ -248,6 +258,8 @@ typedef struct mppi_stats {
   double sdf_ms;             /* summed duration of those launches */
   uint64_t solve_launches;   /* timed solve sequences */
   double solve_ms;           /* summed duration of whole solve sequences */
+  uint64_t tune_runs;        /* shapes tuned (mppi_config.wide_region = 0) */
+  uint64_t wide_region;      /* region size of the last H = 512 launch (0: none yet) */
 } mppi_stats;
 
 int mppi_get_stats(mppi_engine* engine, mppi_stats* out);

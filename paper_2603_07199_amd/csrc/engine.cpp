@@ -161,6 +161,9 @@ struct mppi_engine {
   char* pin_na = nullptr;
   size_t pin_na_bytes = 0;
   mppi_stats stats{};
+  // H = 512 decoder: region size per (precision, H, G, T) of a launch, tuned
+  // on the first launch of that shape unless the config fixes it
+  std::unordered_map<uint64_t, int> wide_tuned;
   std::atomic<int> sticky{0};
   std::mutex mu;                // guards everything above and below
   // served path
@@ -612,6 +615,33 @@ int stage(mppi_engine* e, const std::vector<const mppi_request*>& reqs, bool wan
   return MPPI_OK;
 }
 
+// Region size of the H = 512 decoder for a launch of max shape (maxG, maxT):
+// the config's, else the tuned one for (precision, H, maxG, maxT), tuned now
+// (synchronously, on the batch's own inputs) when allowed, else the default.
+int wide_region_for(mppi_engine* e, const FusedBatch& fb, int n_solves, int maxT, int maxG, int maxTiles,
+                    hipStream_t st, bool may_tune, int* out) {
+  *out = 4;
+  if (e->H != 512) return MPPI_OK;
+  if (e->cfg.wide_region != 0) {
+    *out = e->cfg.wide_region;
+  } else {
+    const uint64_t key = ((uint64_t)(uint32_t)e->cfg.precision << 32) | ((uint64_t)e->H << 16) |
+                         ((uint64_t)maxG << 8) | (uint64_t)maxT;
+    auto it = e->wide_tuned.find(key);
+    if (it != e->wide_tuned.end()) {
+      *out = it->second;
+    } else if (may_tune) {
+      int best = 4;
+      HIPCHK(e, tune_wide_region(fb, n_solves, e->dw, maxT, maxG, maxTiles, st, &best));
+      e->wide_tuned[key] = best;
+      e->stats.tune_runs++;
+      *out = best;
+    }
+  }
+  e->stats.wide_region = (uint64_t)*out;
+  return MPPI_OK;
+}
+
 // Enqueue every kernel of a staged set on stream st.  t0/t1 (optional) bracket
 // the dominant kernel(s): the SDF kernels of the plain path, the fused kernel.
 int launch_staged(mppi_engine* e, Staged& sg, hipStream_t st, hipEvent_t t0, hipEvent_t t1) {
@@ -627,7 +657,10 @@ int launch_staged(mppi_engine* e, Staged& sg, hipStream_t st, hipEvent_t t0, hip
   }
   Aux& a = sg.aux;
   FusedBatch fb{a.descs, a.tiles, a.n_tiles, a.counter};
-  HIPCHK(e, launch_fused(fb, (int)sg.solves.size(), e->dw, a.maxT, a.maxG, a.maxTiles, st, t0, t1));
+  int rg = 4;
+  const int rc = wide_region_for(e, fb, (int)sg.solves.size(), a.maxT, a.maxG, a.maxTiles, st, true, &rg);
+  if (rc != MPPI_OK) return rc;
+  HIPCHK(e, launch_fused(fb, (int)sg.solves.size(), e->dw, a.maxT, a.maxG, a.maxTiles, st, t0, t1, rg));
   return MPPI_OK;
 }
 
@@ -865,6 +898,7 @@ int mppi_create(const mppi_config* cfg, const mppi_sdf_weights* w, mppi_engine**
   if (c.K_max < 1 || c.K_max > kMaxK || c.T_max < 1 || c.T_max > kMaxT || c.G_max < 1 || c.G_max > kMaxG)
     return MPPI_EINVAL;
   if (c.max_instances < 1 || c.max_inflight < 1 || c.queue_depth < 1) return MPPI_EINVAL;
+  if (c.wide_region != 0 && c.wide_region != 2 && c.wide_region != 4 && c.wide_region != 8) return MPPI_EINVAL;
   if (!(c.mass > 0.0) || !isfin(c.mass) || !isfin(c.gravity)) return MPPI_EINVAL;
   for (int i = 0; i < 4; ++i)
     if (!isfin(c.u_lo[i]) || !isfin(c.u_hi[i]) || c.u_lo[i] > c.u_hi[i]) return MPPI_EINVAL;
@@ -1283,7 +1317,10 @@ int mppi_step_noalloc(mppi_engine* e, const mppi_request* r, mppi_result* out) {
     HIPCHK(e, hipMemcpyAsync(ab, aux_host, aux_bytes, hipMemcpyHostToDevice, st));
     const SolveDesc* dd = (const SolveDesc*)ab;
     FusedBatch fb{dd, (const int2*)(ab + o_tiles), nt, (uint32_t*)(ab + o_cnt)};
-    HIPCHK(e, launch_fused(fb, 1, e->dw, T, G, nt, st, nullptr, nullptr));
+    int rg = 4;
+    const int rc = wide_region_for(e, fb, 1, T, G, nt, st, false, &rg);
+    if (rc != MPPI_OK) return rc;
+    HIPCHK(e, launch_fused(fb, 1, e->dw, T, G, nt, st, nullptr, nullptr, rg));
   } else {
     PlainShape shp{K, T, G, e->cfg.sdf_kind};
     HIPCHK(e, launch_plain((const SolveDesc*)(base + s.lay.desc), shp, e->dw, st, nullptr, nullptr));

@@ -38,8 +38,19 @@ struct FusedBatch {
 
 // n_solves descriptors, max_T / max_G over them, max_tiles = most tiles of
 // one solve.  begin/end (optional) bracket the fused kernel itself.
+// wide_region: the H = 512 decoder's neuron blocks per scheduling region
+// (2, 4 or 8; ignored for H <= 256).
 hipError_t launch_fused(const FusedBatch& b, int n_solves, const DeviceWeights& w, int max_T, int max_G,
-                        int max_tiles, hipStream_t s, hipEvent_t begin, hipEvent_t end);
+                        int max_tiles, hipStream_t s, hipEvent_t begin, hipEvent_t end, int wide_region);
+
+// Times the H = 512 decoder with each region size (2, 4, 8; twice each) on the
+// batch's first tiles (two per compute unit; prep and decoder only, which
+// write nothing but tile partials, costs and field values that the next full
+// launch overwrites) and returns the fastest in *best.  Synchronous.  The
+// region size changes only the order of independent matrix-core products,
+// so every choice gives the same results bit for bit.
+hipError_t tune_wide_region(const FusedBatch& b, int n_solves, const DeviceWeights& w, int max_T, int max_G,
+                            int max_tiles, hipStream_t s, int* best);
 
 // Rollouts per fused tile for a precision / width (the unit of work of the
 // persistent kernel).

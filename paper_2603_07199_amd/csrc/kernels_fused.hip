@@ -1432,7 +1432,10 @@ __global__ __launch_bounds__(kMergeThreads) void k_fused_merge(FusedBatch batch)
 constexpr int kWideWaves = 8;
 constexpr int kWideThreads = 64 * kWideWaves;
 constexpr int kWidePairs = kWideWaves / 2;      // row blocks of 16 per pass
-constexpr int kWideRegion = 4;                  // owned neuron blocks per scheduling region
+// Owned neuron blocks per scheduling region of a K-step (fragment read-ahead
+// depth): 2, 4 or 8, a template parameter of the kernel chosen per shape
+// (see launch_fused).
+constexpr int kWideRegionDefault = 4;
 
 template <int P> __host__ __device__ constexpr int frag_bytes() { return PrecTraits<P>::fp8 ? 8 : 16; }
 
@@ -1600,17 +1603,17 @@ __device__ __forceinline__ void wide_epi_half(const f32x4& acc, const float* hb,
 }
 
 // One K-step of one wave: acc[m] += W(slice)[2 m + par] x operand for its
-// H / 32 neuron blocks, in regions of kWideRegion blocks that read the next
+// H / 32 neuron blocks, in regions of RG blocks that read the next
 // region's weight fragments ahead; the first region also issues the global
 // reads of the next slice, the last one its LDS stores.  prep() forms this
 // wave's half of the next K-step's operand: before the products when VFIRST,
 // after them otherwise.
-template <int P, int H, bool VFIRST, class Prep>
+template <int P, int H, bool VFIRST, int RG, class Prep>
 __device__ __forceinline__ void wide_step(const char* slice, const char* xin, int lane, int par, f32x4 (&acc)[H / 32],
                                           Prep&& prep, SliceCopy<P, H>& pf, const u32x4* gsrc, u32x4* ldst, int tid) {
   using PT = PrecTraits<P>;
   constexpr int NS = PT::splits;
-  constexpr int GR = kWideRegion, NG = H / 32 / GR;
+  constexpr int GR = RG, NG = H / 32 / GR;
   BFragT<P> bf[NS];
 #pragma unroll
   for (int sp = 0; sp < NS; ++sp) {
@@ -1692,7 +1695,7 @@ __device__ __forceinline__ void wide_output_rows(const Views& V, const EdgeConst
   if (lane < kRows && e.g == 0 && e.p < e.Pc && q < e.npos) V.field[q] = best;
 }
 
-template <int P, int H, int NHH, bool VFIRST>
+template <int P, int H, int NHH, bool VFIRST, int RG>
 __device__ __forceinline__ void wide_tile(const Views& V, const DeviceWeights& w, const SolveDesc& d, int npos,
                                           int wave, int lane, int tid) {
   using PT = PrecTraits<P>;
@@ -1727,7 +1730,7 @@ __device__ __forceinline__ void wide_tile(const Views& V, const DeviceWeights& w
     for (int ks = 0; ks < KS; ++ks) {
       const int nxt = ks + 1 < SPP ? ks + 1 : 0;
       SliceCopy<P, H> pf;
-      wide_step<P, H, VFIRST>(V.act + (ks & 1) * SB, xb + (ks & 1) * XB, lane, par, accA, [&]() {
+      wide_step<P, H, VFIRST, RG>(V.act + (ks & 1) * SB, xb + (ks & 1) * XB, lane, par, accA, [&]() {
         if (ks + 1 < KS) {
           wide_l1_half<P, H>(V, pt, ks + 1, hq, par, lane, inv1, xb + ((ks + 1) & 1) * XB);
         } else if (NHH == 1) {
@@ -1748,7 +1751,7 @@ __device__ __forceinline__ void wide_tile(const Views& V, const DeviceWeights& w
       for (int ks = 0; ks < KS; ++ks) {
         const int nxt = KS + ks + 1 < SPP ? KS + ks + 1 : 0;
         SliceCopy<P, H> pf;
-        wide_step<P, H, VFIRST>(V.act + (ks & 1) * SB, xb + (ks & 1) * XB, lane, par, accB, [&]() {
+        wide_step<P, H, VFIRST, RG>(V.act + (ks & 1) * SB, xb + (ks & 1) * XB, lane, par, accB, [&]() {
           if (ks + 1 < KS) {
             wide_epi_half<P>(accA[ks + 1], V.hb, sA, ks + 1, hq, par, lane, invB, xb + ((ks + 1) & 1) * XB);
           } else {
@@ -1767,7 +1770,7 @@ __device__ __forceinline__ void wide_tile(const Views& V, const DeviceWeights& w
   }
 }
 
-template <int P, int H, int NHH>
+template <int P, int H, int NHH, int RG>
 __global__ __launch_bounds__(kWideThreads, 1) void k_wide(FusedBatch batch, DeviceWeights w, int Tm, int Gm,
                                                            int max_tiles) {
   extern __shared__ __align__(16) char lds[];
@@ -1792,8 +1795,8 @@ __global__ __launch_bounds__(kWideThreads, 1) void k_wide(FusedBatch batch, Devi
     tile_prologue(V, d, k0, Re, tick, H, wide_cf_stride<H>() - H);
     // waves w and w + 4 share a SIMD: one forms its operands before its
     // products, the other after
-    if (wave < kWideWaves / 2) wide_tile<P, H, NHH, true>(V, w, d, Re * d.T, wave, lane, tid);
-    else wide_tile<P, H, NHH, false>(V, w, d, Re * d.T, wave, lane, tid);
+    if (wave < kWideWaves / 2) wide_tile<P, H, NHH, true, RG>(V, w, d, Re * d.T, wave, lane, tid);
+    else wide_tile<P, H, NHH, false, RG>(V, w, d, Re * d.T, wave, lane, tid);
     __syncthreads();
     tile_epilogue(V, d, k0, Re, tick);
   }
@@ -1828,7 +1831,7 @@ static hipError_t launch_fused_t(const FusedBatch& b, const DeviceWeights& w, in
   return hipGetLastError();
 }
 
-template <int P, int H, int NHH>
+template <int P, int H, int NHH, int RG>
 static hipError_t launch_wide_t(const FusedBatch& b, const DeviceWeights& w, int Tm, int Gm,
                                 int max_tiles, hipStream_t s) {
   const FusedLds L = wide_lds<P, H, NHH>(Tm, Gm, max_tiles);
@@ -1837,7 +1840,7 @@ static hipError_t launch_wide_t(const FusedBatch& b, const DeviceWeights& w, int
     static int max_set = 0;
     std::lock_guard<std::mutex> lock(mu);
     if ((int)L.total > max_set) {
-      hipError_t e = hipFuncSetAttribute((const void*)k_wide<P, H, NHH>,
+      hipError_t e = hipFuncSetAttribute((const void*)k_wide<P, H, NHH, RG>,
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.total);
       if (e != hipSuccess) return e;
       max_set = (int)L.total;
@@ -1848,14 +1851,14 @@ static hipError_t launch_wide_t(const FusedBatch& b, const DeviceWeights& w, int
   if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return e;
   const int grid = std::max(1, std::min(b.n_tiles, ncu));
-  hipLaunchKernelGGL((k_wide<P, H, NHH>), dim3(grid), dim3(kWideThreads), L.total, s, b, w, Tm, Gm,
+  hipLaunchKernelGGL((k_wide<P, H, NHH, RG>), dim3(grid), dim3(kWideThreads), L.total, s, b, w, Tm, Gm,
                      max_tiles);
   return hipGetLastError();
 }
 
 template <int P>
 static hipError_t launch_fused_p(const FusedBatch& b, const DeviceWeights& w, int Tm, int Gm, int mt,
-                                 hipStream_t s) {
+                                 hipStream_t s, int rg) {
   const int nhh = w.n_hidden - 1;
   const bool pe = w.feat_ksteps > 0;
   if (w.H == 128 && nhh == 1) return pe ? launch_fused_t<P, 128, 1, true>(b, w, Tm, Gm, mt, s) : launch_fused_t<P, 128, 1, false>(b, w, Tm, Gm, mt, s);
@@ -1863,31 +1866,82 @@ static hipError_t launch_fused_p(const FusedBatch& b, const DeviceWeights& w, in
   if (w.H == 256 && nhh == 1) return pe ? launch_fused_t<P, 256, 1, true>(b, w, Tm, Gm, mt, s) : launch_fused_t<P, 256, 1, false>(b, w, Tm, Gm, mt, s);
   if (w.H == 256 && nhh == 2) return pe ? launch_fused_t<P, 256, 2, true>(b, w, Tm, Gm, mt, s) : launch_fused_t<P, 256, 2, false>(b, w, Tm, Gm, mt, s);
   if (pe) return hipErrorInvalidValue;   // the H = 512 decoder has no encoded-point layer 1
-  if (w.H == 512 && nhh == 1) return launch_wide_t<P, 512, 1>(b, w, Tm, Gm, mt, s);
-  if (w.H == 512 && nhh == 2) return launch_wide_t<P, 512, 2>(b, w, Tm, Gm, mt, s);
+  if (w.H == 512) {
+    if (rg != 2 && rg != 4 && rg != 8) return hipErrorInvalidValue;
+    if (nhh == 1)
+      return rg == 2 ? launch_wide_t<P, 512, 1, 2>(b, w, Tm, Gm, mt, s)
+                     : rg == 4 ? launch_wide_t<P, 512, 1, 4>(b, w, Tm, Gm, mt, s) : launch_wide_t<P, 512, 1, 8>(b, w, Tm, Gm, mt, s);
+    if (nhh == 2)
+      return rg == 2 ? launch_wide_t<P, 512, 2, 2>(b, w, Tm, Gm, mt, s)
+                     : rg == 4 ? launch_wide_t<P, 512, 2, 4>(b, w, Tm, Gm, mt, s) : launch_wide_t<P, 512, 2, 8>(b, w, Tm, Gm, mt, s);
+  }
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_fused(const FusedBatch& b, int n_solves, const DeviceWeights& w, int max_T, int max_G,
-                        int max_tiles, hipStream_t s, hipEvent_t begin, hipEvent_t end) {
+// Zero the counter and fold (prep), then the decoder kernel of the precision.
+static hipError_t launch_prep_decoder(const FusedBatch& b, int n_solves, const DeviceWeights& w, int max_T,
+                                      int max_G, int max_tiles, hipStream_t s, hipEvent_t begin, hipEvent_t end,
+                                      int wide_region) {
   hipLaunchKernelGGL(k_fused_prep, dim3(max_G, n_solves), dim3(256), 0, s, b, w);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (begin && (e = hipEventRecord(begin, s)) != hipSuccess) return e;
   switch (w.precision) {
-    case P_BF16: e = launch_fused_p<P_BF16>(b, w, max_T, max_G, max_tiles, s); break;
-    case P_BF16X2: e = launch_fused_p<P_BF16X2>(b, w, max_T, max_G, max_tiles, s); break;
-    case P_BF16X3: e = launch_fused_p<P_BF16X3>(b, w, max_T, max_G, max_tiles, s); break;
-    case P_FP8: e = launch_fused_p<P_FP8>(b, w, max_T, max_G, max_tiles, s); break;
-    case P_F16X2: e = launch_fused_p<P_F16X2>(b, w, max_T, max_G, max_tiles, s); break;
+    case P_BF16: e = launch_fused_p<P_BF16>(b, w, max_T, max_G, max_tiles, s, wide_region); break;
+    case P_BF16X2: e = launch_fused_p<P_BF16X2>(b, w, max_T, max_G, max_tiles, s, wide_region); break;
+    case P_BF16X3: e = launch_fused_p<P_BF16X3>(b, w, max_T, max_G, max_tiles, s, wide_region); break;
+    case P_FP8: e = launch_fused_p<P_FP8>(b, w, max_T, max_G, max_tiles, s, wide_region); break;
+    case P_F16X2: e = launch_fused_p<P_F16X2>(b, w, max_T, max_G, max_tiles, s, wide_region); break;
     default: return hipErrorInvalidValue;
   }
   if (e != hipSuccess) return e;
   if (end && (e = hipEventRecord(end, s)) != hipSuccess) return e;
+  return hipSuccess;
+}
+
+hipError_t launch_fused(const FusedBatch& b, int n_solves, const DeviceWeights& w, int max_T, int max_G,
+                        int max_tiles, hipStream_t s, hipEvent_t begin, hipEvent_t end, int wide_region) {
+  hipError_t e = launch_prep_decoder(b, n_solves, w, max_T, max_G, max_tiles, s, begin, end, wide_region);
+  if (e != hipSuccess) return e;
   // per workgroup: the reductions, n tile factors, C x L <= kMergeThreads partial sums
   const size_t merge_lds = sizeof(double) * (3 * (kMergeThreads / 64) + (size_t)max_tiles + kMergeThreads);
   hipLaunchKernelGGL(k_fused_merge, dim3(n_solves, merge_groups(max_T)), dim3(kMergeThreads), merge_lds, s, b);
   return hipGetLastError();
+}
+
+hipError_t tune_wide_region(const FusedBatch& b, int n_solves, const DeviceWeights& w, int max_T, int max_G,
+                            int max_tiles, hipStream_t s, int* best) {
+  *best = kWideRegionDefault;
+  if (w.H != 512) return hipSuccess;
+  int ncu = 0, dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  // the first tiles of the batch (longest first), two per compute unit
+  FusedBatch part = b;
+  part.n_tiles = std::min(b.n_tiles, 2 * ncu);
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  if ((e = hipEventCreate(&t0)) != hipSuccess) return e;
+  if ((e = hipEventCreate(&t1)) != hipSuccess) {
+    hipEventDestroy(t0);
+    return e;
+  }
+  float best_ms = INFINITY;
+  for (int rep = 0; rep < 2 && e == hipSuccess; ++rep)
+    for (const int rg : {2, 4, 8}) {
+      e = launch_prep_decoder(part, n_solves, w, max_T, max_G, max_tiles, s, t0, t1, rg);
+      if (e == hipSuccess) e = hipEventSynchronize(t1);
+      float ms = 0.0f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+      if (e != hipSuccess) break;
+      if (ms < best_ms) {
+        best_ms = ms;
+        *best = rg;
+      }
+    }
+  hipEventDestroy(t0);
+  hipEventDestroy(t1);
+  return e;
 }
 
 int fused_tile_rollouts(int, int, int) { return kTileR; }

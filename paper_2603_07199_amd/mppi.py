@@ -47,7 +47,7 @@ class mppi_config(C.Structure):
         ("dynamics", C.c_int32), ("pe_freqs", C.c_int32),
         ("inertia", C.c_double * 3), ("arm_length", C.c_double), ("yaw_coeff", C.c_double),
         ("thrust_max", C.c_double), ("rate_max", C.c_double),
-        ("wave_queries_max", C.c_uint64),
+        ("wave_queries_max", C.c_uint64), ("wide_region", C.c_int32),
     ]
 
 
@@ -89,6 +89,7 @@ class mppi_stats(C.Structure):
         ("failed", C.c_uint64), ("waves", C.c_uint64), ("bytes_in_use", C.c_uint64),
         ("bytes_peak", C.c_uint64), ("budget", C.c_uint64), ("sdf_launches", C.c_uint64),
         ("sdf_ms", C.c_double), ("solve_launches", C.c_uint64), ("solve_ms", C.c_double),
+        ("tune_runs", C.c_uint64), ("wide_region", C.c_uint64),
     ]
 
 
@@ -356,7 +357,8 @@ class Batch:
 def default_config(model, K_max=8192, T_max=64, G_max=8, hidden=256, n_hidden=3,
                    precision="fp32", path="plain", sdf_kind="mlp", max_instances=4096,
                    max_inflight=64, queue_depth=4096, budget=1 << 30, seed=0, timing=False,
-                   stream=None, device_pool=None, device_pool_bytes=0, pe_freqs=0, wave_queries_max=0):
+                   stream=None, device_pool=None, device_pool_bytes=0, pe_freqs=0, wave_queries_max=0,
+                   wide_region=0):
     return {
         "precision": PREC[precision], "path": PATH[path], "sdf_kind": SDF[sdf_kind],
         "hidden": hidden, "n_hidden": n_hidden, "latent_dim": 64,
@@ -375,6 +377,8 @@ def default_config(model, K_max=8192, T_max=64, G_max=8, hidden=256, n_hidden=3,
         "arm_length": float(model.get("arm_length", 0.0)), "yaw_coeff": float(model.get("yaw_coeff", 0.0)),
         "thrust_max": float(model.get("thrust_max", 0.0)), "rate_max": float(model.get("rate_max", 0.0)),
         "wave_queries_max": int(wave_queries_max),
+        # H = 512 decoder: fragment read-ahead region (2, 4, 8; 0 = tuned per shape)
+        "wide_region": int(wide_region),
     }
 
 

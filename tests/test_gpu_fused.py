@@ -342,3 +342,43 @@ def test_f16x2_weight_scaling(H):
         assert e <= max(U0_TOL, 2.0 * floor)
     plain.close()
     eng.close()
+
+
+@pytest.mark.parametrize("precision", ["bf16", "bf16x3"])
+def test_h512_region_sizes_agree_and_tuning(precision):
+    """The H = 512 decoder's region size (how far ahead a wave reads its
+    weight fragments: 2, 4 or 8) only reorders independent matrix-core
+    products, so every forced choice and the tuned one give the same U*,
+    costs and field values bit for bit; the tuned engine tunes once per shape
+    and keeps a valid choice; the tuned result passes the oracle gate; any
+    other region size is refused."""
+    M = require_gpu()
+    layers = (67, 512, 512, 512, 1)
+    W, b = sc.xavier_weights(layers, seed=9, bias_scale=0.2)
+    kw = dict(K_max=300, T_max=12, G_max=3, hidden=512, n_hidden=3, precision=precision, path="fused",
+              budget=512 << 20)
+    prob = sc.make_problem(300, 12, 3, rot="haar", start="moving", seed=4, d_safe=1.0, instance_id=900)
+    outs = {}
+    for rg in (2, 4, 8, 0):
+        eng = M.Engine((W, b), sc.MODEL, wide_region=rg, **kw)
+        out = eng.step(prob, exports=True)
+        assert out["rc"] == 0
+        st = eng.stats()
+        if rg == 0:
+            assert st["tune_runs"] == 1 and st["wide_region"] in (2, 4, 8)
+            again = eng.step(prob, exports=True)
+            assert again["rc"] == 0 and eng.stats()["tune_runs"] == 1
+            say(f"{precision} H=512: tuned region {st['wide_region']}")
+        else:
+            assert st["tune_runs"] == 0 and st["wide_region"] == rg
+        outs[rg] = out
+        eng.close()
+    for rg in (2, 8, 0):
+        for key in ("U_star", "J", "sdf"):
+            assert np.array_equal(outs[rg][key], outs[4][key]), (rg, key)
+    ref = oracle.solve(prob, (W, b), sc.MODEL, contract=CONTRACT[precision], near_ties=WINDOW.get(precision, False))
+    e, note = _gate(precision, prob, outs[0], ref, f"{precision} H=512 tuned")
+    say(f"{precision} H=512 tuned: u0 err {e:.2e}, {note}")
+    assert e <= U0_TOL
+    with pytest.raises(M.MPPIError):
+        M.Engine((W, b), sc.MODEL, wide_region=3, **kw)
