@@ -86,9 +86,14 @@ __device__ __forceinline__ void fold_gate(const SolveDesc& d, int g, const Devic
   }
   const float* z = d.z + g * kLatent;
   for (int m = threadIdx.x; m < d.H; m += blockDim.x) {
-    // (the transposed block: neighbouring threads read neighbouring words)
+    // (the transposed block: neighbouring threads read neighbouring words;
+    // all 64 reads go out before the first product, one memory latency)
+    double wv[kLatent];
+#pragma unroll
+    for (int j = 0; j < kLatent; ++j) wv[j] = w.w0lat[(size_t)j * d.H + m];
     double acc = w.b0[m];
-    for (int j = 0; j < kLatent; ++j) acc = fma(w.w0lat[(size_t)j * d.H + m], (double)z[j], acc);
+#pragma unroll
+    for (int j = 0; j < kLatent; ++j) acc = fma(wv[j], (double)z[j], acc);
     d.cfold[g * d.H + m] = (float)acc;
     if (cache) cache[m] = (float)acc;
   }

@@ -382,3 +382,22 @@ def test_h512_region_sizes_agree_and_tuning(precision):
     assert e <= U0_TOL
     with pytest.raises(M.MPPIError):
         M.Engine((W, b), sc.MODEL, wide_region=3, **kw)
+
+
+@pytest.mark.parametrize("precision", ["bf16x3", "bf16"])
+def test_fused_long_horizons(precision):
+    """Horizons up to the maximum (T = 128): the tile dynamics run as scans
+    with chunks of ceil(T / 32) steps per lane (here 4, and a ragged last
+    chunk at T = 97); field values, costs and u*_0 against the oracle."""
+    M = require_gpu()
+    layers = (67, 128, 128, 1)
+    eng, w = _engine(M, layers, precision, 64, 128, 2, wseed=11, bias=0.2)
+    for K, T in ((64, 128), (33, 97)):
+        prob = sc.make_problem(K, T, 2, rot="haar", start="moving", seed=T, d_safe=1.0, instance_id=950 + T)
+        ref = oracle.solve(prob, w, sc.MODEL, contract=CONTRACT[precision], near_ties=WINDOW.get(precision, False))
+        out = eng.step(prob, exports=True)
+        assert out["rc"] == 0
+        e, note = _gate(precision, prob, out, ref, f"{precision} T={T}")
+        say(f"fused {precision} K={K} T={T}: u0 err {e:.2e}, {note}")
+        assert e <= U0_TOL
+    eng.close()
