@@ -93,6 +93,10 @@ typedef enum mppi_dynamics {
 
 /* Config flags. */
 #define MPPI_CFG_TIMING (1u << 0)  /* record per-kernel HIP event times (see mppi_get_stats) */
+/* Served path on the fused decoder: one batched launch per admission pass
+ * (up to three in flight on their own streams) instead of the work ring that
+ * a persistent kernel serves (the default where it exists: H <= 256). */
+#define MPPI_CFG_SERVE_BATCHES (1u << 1)
 
 /* Create-time configuration (immutable for the engine's life). */
 typedef struct mppi_config {
@@ -125,10 +129,10 @@ typedef struct mppi_config {
   /* MPPI_DYN_ROTOR_RATES only (all > 0): principal inertia (kg m^2), arm
    * length (m), yaw drag torque per thrust (m), thrust and body-rate bounds */
   double inertia[3], arm_length, yaw_coeff, thrust_max, rate_max;
-  /* Served path: the most work one batch launch takes, in decoder query
-   * points (K T G summed over its solves); a batch always takes at least the
-   * oldest admissible request.  Bounds how long a request waits behind a
-   * burst.  0 = the default, 2^21 query points. */
+  /* Served path in batches (no work ring): the most work one batch launch
+   * takes, in decoder query points (K T G summed over its solves); a batch
+   * always takes at least the oldest admissible request.  Bounds how long a
+   * request waits behind a burst.  0 = the default, 2^21 query points. */
   uint64_t wave_queries_max;
   /* Fused path, H = 512 (weights streamed through LDS): neuron blocks per
    * scheduling region of a K-step, i.e. how far ahead a wave reads its weight
@@ -235,7 +239,17 @@ int mppi_step(mppi_engine* engine, const mppi_request* request, mppi_result* res
 
 /* Queue a solve for the served path and return a ticket at once.  The request
  * is deep-copied.  EAGAIN: the host queue is full.  ENOMEM: the request's
- * device footprint exceeds the whole budget (it could never be admitted). */
+ * device footprint exceeds the whole budget (it could never be admitted).
+ * On the fused decoder with H <= 256 (and no MPPI_CFG_SERVE_BATCHES) the
+ * scheduler publishes each admitted solve as work items (a prep item, then
+ * one item per tile of 16 rollouts) into a ring in pinned host memory that a
+ * persistent kernel consumes while it runs: a request starts on the compute
+ * units that free up next, without a launch of its own, and its result comes
+ * back in pinned memory without a copy.  Results are bit for bit those of
+ * mppi_step.  While that kernel is resident (until about 2 ms after the last
+ * served work) it holds every compute unit, so blocking solves and batches
+ * on the same device wait for it.  Otherwise the served path launches one
+ * batch per admission pass (see wave_queries_max). */
 int mppi_submit(mppi_engine* engine, const mppi_request* request, uint64_t* ticket);
 
 /* MPPI_PENDING while the ticket's solve runs; otherwise copies the outcome
@@ -252,7 +266,8 @@ int mppi_drain(mppi_engine* engine);
  * only with MPPI_CFG_TIMING. */
 typedef struct mppi_stats {
   uint64_t submitted, admitted, completed, failed;
-  uint64_t waves;            /* batched launches of the served path */
+  uint64_t waves;            /* served path: batched launches, or admission passes that published
+                                work into the ring */
   uint64_t bytes_in_use, bytes_peak, budget;
   uint64_t sdf_launches;     /* launches of the dominant (SDF) kernel */
   double sdf_ms;             /* summed duration of those launches */
@@ -260,6 +275,8 @@ typedef struct mppi_stats {
   double solve_ms;           /* summed duration of whole solve sequences */
   uint64_t tune_runs;        /* shapes tuned (mppi_config.wide_region = 0) */
   uint64_t wide_region;      /* region size of the last H = 512 launch (0: none yet) */
+  uint64_t ring_launches;    /* launches of the served ring kernel (it stays resident while work
+                                keeps arriving and ends after about 2 ms without any) */
 } mppi_stats;
 
 int mppi_get_stats(mppi_engine* engine, mppi_stats* out);

@@ -130,6 +130,51 @@ struct Inflight {
   int stream_idx = 0;
 };
 
+// Served work ring (the persistent kernel k_served and its items; see
+// ring.hpp).  One pinned block holds the tails, the lost flag, the items, the
+// slots' completion words and per slot an area with the solve's upload mirror
+// and its result, weights and costs as the kernel writes them; one device
+// block holds the ticket and prep heads, the device copies of the tails and
+// per-slot counters.
+struct RingSolve {
+  std::unique_ptr<Solve> s;
+  uint32_t slot = 0, seq = 0, items = 0;
+};
+
+struct ServedRing {
+  bool on = false;
+  char* pin = nullptr;
+  size_t pin_bytes = 0;
+  intptr_t dev_delta = 0;        // device address of pinned memory minus host address
+  char* dev = nullptr;
+  uint64_t* tail = nullptr;
+  uint64_t* ptail = nullptr;
+  uint32_t* lost = nullptr;
+  uint32_t* done = nullptr;
+  RingItem* items = nullptr;     // tile queue
+  RingItem* pitems = nullptr;    // prep queue
+  uint32_t cap = 0, pcap = 0, nslots = 0, grid = 1;
+  int max_tiles = 1;
+  size_t area_off = 0, slot_bytes = 0, o_res = 0, o_wn = 0, o_J = 0;   // upload mirror at 0
+  uint64_t published = 0, in_use = 0, published_p = 0;
+  uint32_t next_seq = 1;
+  std::vector<uint32_t> free_slots;
+  std::vector<RingSolve> live;
+  hipEvent_t ev = nullptr;
+  bool running = false;
+  bool closing = false;          // exit items of the running launch published
+  uint64_t quiet_since = 0;      // no live solve since then (ns)
+  RingArgs args{};
+  char* area(uint32_t slot) const { return pin + area_off + (size_t)slot * slot_bytes; }
+  template <class T> T* on_device(void* host) const { return (T*)((intptr_t)host + dev_delta); }
+};
+// A launch ends after this long without live solves; polls of a waiting
+// workgroup (about 1 us each) before it gives up; the device's reads of the
+// host tails are at least this many 10 ns ticks apart.
+constexpr uint64_t kRingQuietNs = 2000000;
+constexpr uint32_t kRingWaitPolls = 1u << 23;
+constexpr uint32_t kRingRefreshTicks = 100;
+
 }  // namespace
 
 struct mppi_engine {
@@ -176,6 +221,7 @@ struct mppi_engine {
   std::vector<Inflight> inflight;
   std::unordered_map<uint64_t, std::unique_ptr<Solve>> done;
   std::unordered_map<uint64_t, uint64_t> ticket_submit_ns;
+  ServedRing ring;              // served path through the work ring (fused, H <= 256)
 };
 
 struct mppi_batch {
@@ -852,6 +898,9 @@ int upload_weights(mppi_engine* e, const mppi_sdf_weights* w) {
 }
 
 void scheduler_loop(mppi_engine* e);
+int ring_setup(mppi_engine* e);
+void ring_free(mppi_engine* e);
+int ring_end_launch(mppi_engine* e);
 
 }  // namespace
 
@@ -939,6 +988,7 @@ int mppi_create(const mppi_config* cfg, const mppi_sdf_weights* w, mppi_engine**
     if (e->instTick) hipFree(e->instTick);
     if (e->instCf) hipFree(e->instCf);
     if (e->pin_na) hipHostFree(e->pin_na);
+    ring_free(e.get());
     return rc;
   };
   hipStream_t s0 = (hipStream_t)c.stream;
@@ -1006,6 +1056,18 @@ int mppi_create(const mppi_config* cfg, const mppi_sdf_weights* w, mppi_engine**
   const uint64_t budget = c.hbm_budget_bytes ? std::min<uint64_t>(c.hbm_budget_bytes, e->pool_bytes) : e->pool_bytes;
   e->stats.budget = budget;
   e->adm = std::make_unique<Admission>(budget, c.max_inflight, c.queue_depth);
+  // served requests go through the work ring where the persistent kernel
+  // exists for this decoder (H <= 256) unless the config asks for batches
+  if (e->fused && !(c.flags & MPPI_CFG_SERVE_BATCHES)) {
+    const int tr = tile_rollouts(e.get(), c.G_max);
+    const int feat_ks = c.pe_freqs > 0 ? (3 + 6 * c.pe_freqs + 31) / 32 : 0;
+    const size_t lds = served_lds_bytes(c.precision, c.hidden, c.n_hidden, c.T_max, c.G_max,
+                                        (c.K_max + tr - 1) / tr, feat_ks);
+    if (lds > 0 && lds <= kMaxLdsBytes) {
+      rc = ring_setup(e.get());
+      if (rc != MPPI_OK) return bail(rc);
+    }
+  }
   if (hipDeviceSynchronize() != hipSuccess) return bail(MPPI_EDEVICE);
   mppi_engine* raw = e.release();
   raw->sched = std::thread(scheduler_loop, raw);
@@ -1035,6 +1097,7 @@ int mppi_destroy(mppi_engine* e) {
   for (char* p : e->pin)
     if (p) hipHostFree(p);
   if (e->pin_na) hipHostFree(e->pin_na);
+  ring_free(e);
   delete e;
   return MPPI_OK;
 }
@@ -1044,6 +1107,7 @@ int mppi_step(mppi_engine* e, const mppi_request* r, mppi_result* out) {
   if (e->sticky.load()) return MPPI_EDEVICE;
   std::lock_guard<std::mutex> lk(e->mu);
   hipSetDevice(e->dev);
+  if (ring_end_launch(e) != MPPI_OK) return MPPI_EDEVICE;
   const uint64_t t_submit = now_ns();
   Staged sg;
   const bool exports = out->samples || out->positions || out->sdf;
@@ -1130,7 +1194,9 @@ int mppi_poll(mppi_engine* e, uint64_t ticket, mppi_result* out) {
 int mppi_drain(mppi_engine* e) {
   if (!e) return MPPI_EINVAL;
   std::unique_lock<std::mutex> lk(e->mu);
-  e->cv.wait(lk, [&] { return e->sticky.load() != 0 || (e->adm->queued() == 0 && e->inflight.empty()); });
+  e->cv.wait(lk, [&] {
+    return e->sticky.load() != 0 || (e->adm->queued() == 0 && e->inflight.empty() && e->ring.live.empty());
+  });
   return e->sticky.load() ? MPPI_EDEVICE : MPPI_OK;
 }
 
@@ -1201,6 +1267,8 @@ int mppi_batch_run(mppi_engine* e, mppi_batch* b) {
   if (!e || !b) return MPPI_EINVAL;
   if (e->sticky.load()) return MPPI_EDEVICE;
   std::lock_guard<std::mutex> lk(e->mu);
+  hipSetDevice(e->dev);
+  if (ring_end_launch(e) != MPPI_OK) return MPPI_EDEVICE;
   hipStream_t st = e->streams[0];
   const bool timing = e->cfg.flags & MPPI_CFG_TIMING;
   if (timing && b->launched) {
@@ -1274,6 +1342,7 @@ int mppi_step_noalloc(mppi_engine* e, const mppi_request* r, mppi_result* out) {
   // one user of this device's scratch at a time within the process
   std::lock_guard<std::mutex> dk(scratch_use_mutex(e->dev));
   hipSetDevice(e->dev);
+  if (ring_end_launch(e) != MPPI_OK) return MPPI_EDEVICE;
   const uint64_t t_submit = now_ns();
   double Lo[16];
   int rc = validate(e, r, Lo);
@@ -1356,11 +1425,358 @@ int mppi_step_noalloc(mppi_engine* e, const mppi_request* r, mppi_result* out) {
 
 namespace {
 
+// ---------------------------------------------------------------- work ring
+// Pinned and device blocks of the ring, sized for max_inflight solves of the
+// largest accepted shape (every slot's items fit: tile queue slots x tiles,
+// prep queue one per slot).
+int ring_setup(mppi_engine* e) {
+  ServedRing& R = e->ring;
+  const mppi_config& c = e->cfg;
+  R.nslots = (uint32_t)std::min(c.max_inflight, 1024);
+  const int tr = tile_rollouts(e, c.G_max);
+  R.max_tiles = (c.K_max + tr - 1) / tr;
+  int ncu = 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, e->dev) != hipSuccess || ncu < 1)
+    return MPPI_EDEVICE;
+  R.grid = (uint32_t)ncu;
+  R.cap = R.nslots * (uint32_t)R.max_tiles + R.grid;   // live solves' tiles and one launch's exits
+  R.pcap = R.nslots;
+  size_t o = align_up(layout_for(e, c.K_max, c.T_max, c.G_max).upload_bytes);
+  R.o_res = o;
+  o += align_up(sizeof(double) * (4 * (size_t)c.T_max + RES_SCALARS));
+  R.o_wn = o;
+  o += align_up(sizeof(double) * (size_t)c.K_max);
+  R.o_J = o;
+  o += align_up(sizeof(float) * (size_t)c.K_max);
+  R.slot_bytes = o;
+  const size_t o_items = kAlign;
+  const size_t o_pitems = align_up(o_items + sizeof(RingItem) * (size_t)R.cap);
+  const size_t o_done = align_up(o_pitems + sizeof(RingItem) * (size_t)R.pcap);
+  R.area_off = align_up(o_done + sizeof(uint32_t) * R.nslots);
+  R.pin_bytes = R.area_off + R.slot_bytes * R.nslots;
+  if (hipHostMalloc((void**)&R.pin, R.pin_bytes, hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess) {
+    R.pin = nullptr;
+    return MPPI_ENOMEM;
+  }
+  memset(R.pin, 0, R.pin_bytes);
+  void* dp = nullptr;
+  if (hipHostGetDevicePointer(&dp, R.pin, 0) != hipSuccess) return MPPI_EDEVICE;
+  R.dev_delta = (intptr_t)dp - (intptr_t)R.pin;
+  R.tail = (uint64_t*)R.pin;
+  R.ptail = (uint64_t*)(R.pin + 8);
+  R.lost = (uint32_t*)(R.pin + 16);
+  R.items = (RingItem*)(R.pin + o_items);
+  R.pitems = (RingItem*)(R.pin + o_pitems);
+  R.done = (uint32_t*)(R.pin + o_done);
+  const size_t dbytes = 64 + sizeof(uint32_t) * 3 * (size_t)R.nslots;
+  if (hipMalloc((void**)&R.dev, dbytes) != hipSuccess) {
+    R.dev = nullptr;
+    return MPPI_ENOMEM;
+  }
+  if (hipMemset(R.dev, 0, dbytes) != hipSuccess) return MPPI_EDEVICE;
+  if (hipEventCreateWithFlags(&R.ev, hipEventDisableTiming) != hipSuccess) {
+    R.ev = nullptr;
+    return MPPI_EDEVICE;
+  }
+  RingArgs& a = R.args;
+  a.pool = e->pool;
+  a.items = R.on_device<const RingItem>(R.items);
+  a.pitems = R.on_device<const RingItem>(R.pitems);
+  a.tail = R.on_device<const uint64_t>(R.tail);
+  a.ptail = R.on_device<const uint64_t>(R.ptail);
+  a.lost = R.on_device<uint32_t>(R.lost);
+  a.done = R.on_device<uint32_t>(R.done);
+  a.head = (uint64_t*)R.dev;
+  a.phead = (uint64_t*)(R.dev + 8);
+  a.dtail = (uint64_t*)(R.dev + 16);
+  a.dptail = (uint64_t*)(R.dev + 24);
+  a.poll_time = (uint64_t*)(R.dev + 32);
+  a.poll = (uint32_t*)(R.dev + 40);
+  a.prep = (uint32_t*)(R.dev + 64);
+  a.tiles = a.prep + R.nslots;
+  a.fail = a.tiles + R.nslots;
+  a.cap = R.cap;
+  a.pcap = R.pcap;
+  a.refresh_ticks = kRingRefreshTicks;
+  a.wait_polls = kRingWaitPolls;
+  R.free_slots.clear();
+  for (uint32_t i = 0; i < R.nslots; ++i) R.free_slots.push_back(R.nslots - 1 - i);
+  R.on = true;
+  return MPPI_OK;
+}
+
+void ring_free(mppi_engine* e) {
+  ServedRing& R = e->ring;
+  if (R.ev) hipEventDestroy(R.ev);
+  if (R.dev) hipFree(R.dev);
+  if (R.pin) hipHostFree(R.pin);
+  R.ev = nullptr;
+  R.dev = nullptr;
+  R.pin = nullptr;
+  R.on = false;
+}
+
+// A ticket that fails before it reaches the device: its result carries rc.
+void fail_ticket(mppi_engine* e, const AdmissionItem& a, int rc) {
+  auto s = std::make_unique<Solve>();
+  s->ticket = a.ticket;
+  s->T = e->pending[a.ticket].req.T;
+  s->res.assign(4 * s->T + RES_SCALARS, 0.0);
+  s->res[4 * s->T + RES_STATUS] = rc;
+  s->want_w = s->want_J = false;
+  s->t_submit = e->ticket_submit_ns[a.ticket];
+  s->t_done = now_ns();
+  e->adm->complete(a.footprint);
+  e->stats.failed++;
+  e->done[a.ticket] = std::move(s);
+  e->pending.erase(a.ticket);
+}
+
+// Validate, bind the instance, allocate the device block and pack one request
+// into the pinned mirror of ring slot `slot`; its descriptor sends the result,
+// the weights and a copy of the costs to the slot's pinned areas.
+int ring_stage(mppi_engine* e, const mppi_request* r, uint32_t slot, std::unique_ptr<Solve>& out) {
+  ServedRing& R = e->ring;
+  double Lo[16];
+  int rc = validate(e, r, Lo);
+  auto s = std::make_unique<Solve>();
+  s->K = r->K;
+  s->T = r->T;
+  s->G = r->G;
+  s->flags = r->flags;
+  s->want_w = s->want_J = true;
+  s->exports = false;
+  if (rc == MPPI_OK) rc = acquire_slot(e, r->instance_id, &s->slot);
+  if (rc == MPPI_OK && e->inst[s->slot].busy) rc = MPPI_EAGAIN;
+  if (rc == MPPI_OK && !gates_cached_ok(e, r)) rc = MPPI_EINVAL;
+  if (rc == MPPI_OK) {
+    s->lay = layout_for(e, r->K, r->T, r->G, false);
+    if (!e->arena.alloc(s->lay.total, &s->off)) return MPPI_ENOMEM;
+    s->bytes = s->lay.total;
+  }
+  if (rc != MPPI_OK) return rc;
+  e->inst[s->slot].busy = true;
+  char* area = R.area(slot);
+  pack_solve(e, r, s.get(), Lo, e->pool + s->off, area);
+  SolveDesc& d = s->desc;
+  d.result = R.on_device<double>(area + R.o_res);
+  d.wn = R.on_device<double>(area + R.o_wn);
+  d.J_copy = R.on_device<float>(area + R.o_J);
+  memcpy(area + s->lay.desc, &d, sizeof(SolveDesc));
+  out = std::move(s);
+  return MPPI_OK;
+}
+
+// Items of a staged solve: its prep item into the prep queue, one item per
+// tile into the tile queue (published by the caller).
+void ring_write_items(mppi_engine* e, RingSolve& rs) {
+  ServedRing& R = e->ring;
+  const Solve* s = rs.s.get();
+  const uint64_t block = s->off;
+  const uint32_t nt = (uint32_t)s->desc.n_tiles, tr = (uint32_t)s->desc.tile_rollouts;
+  R.pitems[R.published_p++ % R.pcap] = RingItem{block, (uint64_t)(uintptr_t)R.on_device<char>(R.area(rs.slot)),
+                                                rs.slot, -1, (uint32_t)s->lay.upload_bytes, rs.seq};
+  for (uint32_t t = 0; t < nt; ++t)
+    R.items[R.published++ % R.cap] = RingItem{block, 0, rs.slot, (int32_t)(t * tr), nt, rs.seq};
+  rs.items = nt;
+  R.in_use += rs.items;
+}
+
+// Solves whose completion word carries their sequence number: results from
+// the slot's pinned areas, memory, instance and slot released.
+bool ring_retire(mppi_engine* e) {
+  ServedRing& R = e->ring;
+  bool any = false;
+  for (size_t i = 0; i < R.live.size();) {
+    RingSolve& rs = R.live[i];
+    const uint32_t w = __atomic_load_n(R.done + rs.slot, __ATOMIC_ACQUIRE);
+    if ((w & ~kRingFailBit) != rs.seq) {
+      ++i;
+      continue;
+    }
+    Solve* s = rs.s.get();
+    const char* area = R.area(rs.slot);
+    const double* res = (const double*)(area + R.o_res);
+    s->res.assign(res, res + 4 * s->T + RES_SCALARS);
+    s->wn.assign((const double*)(area + R.o_wn), (const double*)(area + R.o_wn) + s->K);
+    s->J.assign((const float*)(area + R.o_J), (const float*)(area + R.o_J) + s->K);
+    if (w & kRingFailBit) {
+      // a tile never saw the solve's block: the device is not trusted any
+      // more, and the block stays allocated (a late copy could still land)
+      s->res[4 * s->T + RES_STATUS] = MPPI_EDEVICE;
+      e->sticky.store(MPPI_EDEVICE);
+    } else {
+      e->arena.release(s->off, s->bytes);
+    }
+    s->bytes = 0;
+    if (s->slot >= 0) e->inst[s->slot].busy = false;
+    s->t_done = now_ns();
+    note_result(e, s);
+    e->adm->complete(s->footprint);
+    if ((int)s->res[4 * s->T + RES_STATUS] != MPPI_OK) e->stats.failed++;
+    e->stats.completed++;
+    R.in_use -= rs.items;
+    R.free_slots.push_back(rs.slot);
+    e->done[s->ticket] = std::move(rs.s);
+    R.live.erase(R.live.begin() + i);
+    any = true;
+  }
+  if (any) e->cv.notify_all();
+  return any;
+}
+
+// Exit items for every workgroup of the running launch (see ring.hpp).
+void ring_publish_exits(mppi_engine* e) {
+  ServedRing& R = e->ring;
+  for (uint32_t i = 0; i < R.grid; ++i)
+    R.items[R.published++ % R.cap] = RingItem{0, 0, 0, kRingExit, 0, 0};
+  __atomic_store_n(R.tail, R.published, __ATOMIC_RELEASE);
+  R.closing = true;
+}
+
+// Called with the engine lock held by a path that launches kernels of its
+// own (blocking solve, staged batch): the ring kernel holds every compute
+// unit while it runs, so its launch ends first.  Its exit items go behind
+// everything already published, which the kernel finishes without the host;
+// the scheduler retires those solves as usual.
+int ring_end_launch(mppi_engine* e) {
+  ServedRing& R = e->ring;
+  if (!R.on || !R.running) return MPPI_OK;
+  if (!R.closing) ring_publish_exits(e);
+  const hipError_t err = hipEventSynchronize(R.ev);
+  if (err != hipSuccess || __atomic_load_n(R.lost, __ATOMIC_ACQUIRE)) {
+    e->sticky.store(MPPI_EDEVICE);
+    return MPPI_EDEVICE;
+  }
+  R.running = false;
+  R.closing = false;
+  R.in_use -= R.grid;
+  return MPPI_OK;
+}
+
+// Served path through the work ring.  Each pass: note whether the ring
+// kernel still runs, retire completed solves, admit what fits (budget and
+// ring slots) and publish it, start a launch when published work has no
+// running kernel, and end the launch once no solve has been live for a
+// while (or at destroy).  The kernel stays resident while work keeps coming.
+void scheduler_loop_ring(mppi_engine* e) {
+  hipSetDevice(e->dev);
+  ServedRing& R = e->ring;
+  hipStream_t st = e->streams[1];
+  std::unique_lock<std::mutex> lk(e->mu);
+  int idle_passes = 0;
+  uint64_t stop_deadline = 0;   // destroy waits this long for running solves
+  while (true) {
+    const uint64_t now = now_ns();
+    if (e->stop && !stop_deadline) stop_deadline = now + 30ull * 1000000000ull;
+    if (stop_deadline && now > stop_deadline && !R.live.empty()) e->sticky.store(MPPI_EDEVICE);
+    if (R.running) {
+      const hipError_t q = hipEventQuery(R.ev);
+      if (q == hipSuccess) {
+        // a launch ends only through its exit items; anything else (a
+        // workgroup that gave up on its ticket) leaves the ring unusable
+        if (!R.closing || __atomic_load_n(R.lost, __ATOMIC_ACQUIRE)) e->sticky.store(MPPI_EDEVICE);
+        R.running = false;
+        R.closing = false;
+        R.in_use -= R.grid;
+      } else if (q != hipErrorNotReady) {
+        e->sticky.store(MPPI_EDEVICE);
+        R.running = false;
+      }
+    }
+    bool progress = ring_retire(e);
+    if (!R.live.empty()) R.quiet_since = now;
+    if (e->stop && (R.live.empty() || e->sticky.load())) break;
+    if (!e->stop && !e->sticky.load() && !R.free_slots.empty()) {
+      auto adm = e->adm->admit([&](uint64_t id) {
+        const int slot = e->inst_map.find(id);
+        return slot >= 0 && e->inst[slot].busy;
+      });
+      const uint64_t tadm = now_ns();
+      size_t n_pub = 0;
+      for (size_t i = 0; i < adm.size(); ++i) {
+        const AdmissionItem& a = adm[i];
+        const mppi_request* r = &e->pending[a.ticket].req;
+        int rc = MPPI_OK;
+        if (!gates_cached_ok(e, r)) rc = MPPI_EINVAL;
+        else if (!e->inst_map.contains(r->instance_id) && (int)e->inst.size() >= e->cfg.max_instances)
+          rc = MPPI_EAGAIN;
+        std::unique_ptr<Solve> s;
+        const bool no_slot = rc == MPPI_OK && R.free_slots.empty();
+        if (rc == MPPI_OK && !no_slot) rc = ring_stage(e, r, R.free_slots.back(), s);
+        if (no_slot || (rc == MPPI_ENOMEM && (!R.live.empty() || n_pub > 0))) {
+          // admitted by budget but not placeable yet: back to the queue
+          // front until running solves release memory or slots
+          e->adm->requeue_front(std::vector<AdmissionItem>(adm.begin() + i, adm.end()));
+          break;
+        }
+        if (rc != MPPI_OK) {
+          fail_ticket(e, a, rc);
+          continue;
+        }
+        RingSolve rs;
+        rs.slot = R.free_slots.back();
+        R.free_slots.pop_back();
+        rs.seq = R.next_seq;
+        R.next_seq = R.next_seq >= 0x7FFFFFFFu ? 1u : R.next_seq + 1u;
+        s->ticket = a.ticket;
+        s->footprint = a.footprint;
+        s->t_submit = e->ticket_submit_ns[a.ticket];
+        s->t_admit = tadm;
+        rs.s = std::move(s);
+        ring_write_items(e, rs);
+        R.live.push_back(std::move(rs));
+        e->pending.erase(a.ticket);
+        ++n_pub;
+      }
+      if (n_pub) {
+        __atomic_store_n(R.ptail, R.published_p, __ATOMIC_RELEASE);
+        __atomic_store_n(R.tail, R.published, __ATOMIC_RELEASE);
+        e->stats.admitted += n_pub;
+        e->stats.waves++;
+        R.quiet_since = now;
+        progress = true;
+      }
+      e->cv.notify_all();
+    }
+    if (!R.running && !R.live.empty() && !e->sticky.load()) {
+      hipError_t err = launch_served(R.args, e->dw, e->cfg.T_max, e->cfg.G_max, R.max_tiles, st);
+      if (err == hipSuccess) err = hipEventRecord(R.ev, st);
+      if (err != hipSuccess) {
+        e->sticky.store(MPPI_EDEVICE);
+        e->cv.notify_all();
+      } else {
+        R.running = true;
+        R.in_use += R.grid;   // the exit items this launch will take
+        e->stats.ring_launches++;
+      }
+    }
+    // end a quiet launch (or at destroy): its workgroups take one exit each
+    if (R.running && !R.closing && R.live.empty() && (e->stop || now - R.quiet_since >= kRingQuietNs))
+      ring_publish_exits(e);
+    if ((!R.live.empty() || R.running) && !e->sticky.load()) {
+      // poll the completion words: yield first, then short sleeps
+      idle_passes = progress ? 0 : idle_passes + 1;
+      lk.unlock();
+      if (idle_passes < 200) std::this_thread::yield();
+      else std::this_thread::sleep_for(std::chrono::microseconds(20));
+      lk.lock();
+    } else {
+      idle_passes = 0;
+      e->cv.wait(lk, [&] { return e->stop || e->adm->queued() > 0 || e->sticky.load(); });
+      if (e->sticky.load() && !e->stop) e->cv.wait(lk, [&] { return e->stop; });
+    }
+  }
+  // a launch still running takes its exits now (destroy synchronises the stream)
+  if (R.running && !R.closing) ring_publish_exits(e);
+}
+
 // Served path.  Each pass: retire finished batches (their budget, instances
 // and results are released), then admit whatever fits and launch it as one
 // batch on a free serving stream.  Requests arriving while batches run are
 // admitted into the next batch as memory and streams free up.
 void scheduler_loop(mppi_engine* e) {
+  if (e->ring.on) return scheduler_loop_ring(e);
   hipSetDevice(e->dev);
   const int nstreams = (int)e->streams.size() - 1;
   const bool timing = e->cfg.flags & MPPI_CFG_TIMING;

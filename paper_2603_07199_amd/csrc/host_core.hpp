@@ -9,6 +9,8 @@
 #include <map>
 #include <vector>
 
+#include "solve_desc.hpp"
+
 namespace mppi {
 
 constexpr uint64_t kAlign = 256;
@@ -138,7 +140,7 @@ inline SolveLayout solve_layout(int K, int T, int G, int H, bool fused, int n_ti
   SolveLayout L{};
   uint64_t o = 0;
   auto take = [&](uint64_t bytes) { const uint64_t r = o; o = align_up(o + bytes); return r; };
-  L.desc = take(512);
+  L.desc = take(sizeof(SolveDesc));
   L.U = take(8ull * 4 * T);
   L.Rt = take(4ull * 9 * G);
   L.base = take(4ull * 3 * G * (T + 1));

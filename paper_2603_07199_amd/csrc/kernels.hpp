@@ -8,6 +8,7 @@
 
 #include "../../include/mppi.h"
 
+#include "ring.hpp"
 #include "solve_desc.hpp"
 #include "weights.hpp"
 
@@ -51,6 +52,15 @@ hipError_t launch_fused(const FusedBatch& b, int n_solves, const DeviceWeights& 
 // so every choice gives the same results bit for bit.
 hipError_t tune_wide_region(const FusedBatch& b, int n_solves, const DeviceWeights& w, int max_T, int max_G,
                             int max_tiles, hipStream_t s, int* best);
+
+// Served path: the persistent ring kernel (see ring.hpp), one workgroup per
+// compute unit, for H <= 256; it runs until the ring's stop word is set or
+// its workgroups find no item for the ring's idle_polls polls.  max_T,
+// max_G, max_tiles: the largest solve the engine accepts (LDS layout).
+hipError_t launch_served(const RingArgs& r, const DeviceWeights& w, int max_T, int max_G, int max_tiles,
+                         hipStream_t s);
+// LDS bytes of one served workgroup (0: no served kernel for this width).
+size_t served_lds_bytes(int precision, int H, int n_hidden, int Tm, int Gm, int max_tiles, int feat_ks);
 
 // Rollouts per fused tile for a precision / width (the unit of work of the
 // persistent kernel).

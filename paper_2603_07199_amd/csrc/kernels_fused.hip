@@ -55,6 +55,7 @@
 
 #include "device_common.hpp"
 #include "kernels.hpp"
+#include "ring.hpp"
 #include "weights.hpp"
 
 namespace mppi {
@@ -1199,6 +1200,59 @@ __device__ __forceinline__ void decoder_tile(const Views& V, const SolveDesc& d,
   }
 }
 
+// The steps of k_fused below as functions, for the served ring kernel
+// (k_fused keeps them written out).  Once per kernel: the weights of the
+// owned neurons into VGPRs (resident for the whole kernel) and the small
+// per-network tables into LDS; returns the owned layer's scale.
+template <int P, int H, int NHH, bool PE, int MB>
+__device__ __forceinline__ float fused_setup(const Views& V, const DeviceWeights& w, int tid, int lane, int own,
+                                             int gw, FragT<P> (&wreg)[MB][H / 32]) {
+  using PT = PrecTraits<P>;
+  // feature table: padding features (past 3 + 6F) must read as zero
+  if constexpr (PE)
+    for (int i = tid; i < (int)(3 * pe_slot_bytes(w.feat_k32) / 4); i += kThreads) ((uint32_t*)V.feat)[i] = 0u;
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+    for (int ks = 0; ks < H / 32; ++ks) {
+      const size_t fi = frag_index<H>(own, gw * MB + mb, ks, lane);
+      if constexpr (PT::fp8) wreg[mb][ks] = ((const long*)w.hidden_lp)[fi];
+      else wreg[mb][ks] = __builtin_bit_cast(FragT<P>, ((const uint4*)w.hidden_lp)[fi]);
+    }
+  const float scale_own = PT::scaled ? w.w_scale[own] * w.a_scale[own] : 1.0f;
+  for (int i = tid; i < 4 * H; i += kThreads) V.w1p[i] = w.w1p[i];
+  for (int i = tid; i < NHH * H; i += kThreads) V.hb[i] = bias_start<P>(w.hbias[i], PT::scaled ? w.w_scale[i / H] : 1.0f);
+  for (int i = tid; i < H; i += kThreads) V.wo[i] = w.wout[i];
+  return scale_own;
+}
+
+// One tile: the 16 rollouts of solve d from rollout k0 (noise, dynamics,
+// decoder, costs, the tile's FP64 partial); every thread of the workgroup.
+template <int P, int H, int NHH, bool PE, int MB>
+__device__ __forceinline__ void fused_tile(const Views& V, const SolveDesc& d, const DeviceWeights& w, int k0,
+                                           int wave, int lane, int gw, int h, int nl, float scale_own,
+                                           const FragT<P> (&wreg)[MB][H / 32]) {
+  const int K = d.K, T = d.T, G = d.G;
+  const int Re = min(kTileR, K - k0);
+  const uint32_t tick = d.tick_fixed == 0xFFFFFFFFu ? *d.tick_slot : d.tick_fixed;
+  tile_prologue(V, d, k0, Re, tick, H);
+  const int npos = Re * T;
+  const int nblk = (npos + kRows / G - 1) / (kRows / G);
+  // waves w and w + 4 share a SIMD: the second runs its products first
+  // (with two hidden layers that is the owner of the last one, whose
+  // epilogue needs the fewest registers beside two accumulator sets)
+  // (waves 0 and kWaves / 2 - 1, vector first, also carry the edge work)
+  if (wave >= kWaves / 2)
+    decoder_tile<P, H, NHH, NHH - 1, true, MB, PE, 0>(V, d, w, wave, lane, gw, h, nl, scale_own, wreg, npos, nblk);
+  else if (wave == 0)
+    decoder_tile<P, H, NHH, 0, false, MB, PE, 1>(V, d, w, wave, lane, gw, h, nl, scale_own, wreg, npos, nblk);
+  else if (wave == kWaves / 2 - 1)
+    decoder_tile<P, H, NHH, 0, false, MB, PE, 2>(V, d, w, wave, lane, gw, h, nl, scale_own, wreg, npos, nblk);
+  else
+    decoder_tile<P, H, NHH, 0, false, MB, PE, 0>(V, d, w, wave, lane, gw, h, nl, scale_own, wreg, npos, nblk);
+  tile_epilogue(V, d, k0, Re, tick);
+}
+
 template <int P, int H, int NHH, bool PE>
 __global__ __launch_bounds__(kThreads, 1) void k_fused(FusedBatch batch, DeviceWeights w, int Tm, int Gm,
                                                         int max_tiles) {
@@ -1288,59 +1342,72 @@ __host__ __device__ constexpr int merge_groups(int T) { return (4 * T + kMergeSl
 // C consecutive tile ranges, each summed in tile order, then the ranges in
 // order, with C a function of T and the tile count only: the result does not
 // depend on which workgroup ran which tile or on what else was in the batch.
-__global__ __launch_bounds__(kMergeThreads) void k_fused_merge(FusedBatch batch) {
-  extern __shared__ __align__(16) char lds[];
-  constexpr int NW = kMergeThreads / 64;
-  const SolveDesc& d = batch.descs[blockIdx.x];
+// Merge group c of solve d on a workgroup of NT threads (NT = kMergeThreads,
+// or fewer: then each thread plays kMergeThreads / NT of the threads above,
+// and every sum keeps the order of kMergeThreads threads, so the result is
+// the same bit for bit).  `lds` holds 3 kMergeThreads / 64 + kMergeThreads
+// doubles, `fac` the solve's n tile factors.
+template <int NT>
+__device__ void merge_group(const SolveDesc& d, int c, double* lds, double* fac, bool reuse = false) {
+  constexpr int VT = kMergeThreads;   // threads whose summation order is kept
+  constexpr int NW = VT / 64;
+  constexpr int R = VT / NT;
+  static_assert(VT % NT == 0 && NT % 64 == 0, "whole waves");
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int n = d.n_tiles, T = d.T, K = d.K;
-  const int ng = merge_groups(T), c = blockIdx.y;
-  if (c >= ng) return;
+  const int ng = merge_groups(T);
   const int nU = 4 * T, L = (nU + ng - 1) / ng, u0 = c * L, u1 = min(nU, u0 + L);
-  const int C = max(1, min(n, kMergeThreads / L));    // tile ranges of the U* sums
-  double* red = (double*)lds;          // 3 NW per-wave partial results
-  double* fac = red + 3 * NW;          // n tile factors
-  double* part = fac + n;              // C x L partial sums of the slice
+  const int C = max(1, min(n, VT / L));    // tile ranges of the U* sums
+  double* red = lds;                  // 3 NW per-wave partial results
+  double* part = red + 3 * NW;        // C x L partial sums of the slice
   // Reads that do not depend on rho go out first, so that their latency
   // passes during the reductions: this thread's U* item (tile range rg,
-  // entry o; C L <= kMergeThreads, so at most one) up to kPre of its tiles,
-  // and the first of its costs for the weights.
-  constexpr int kPre = 16;
+  // entry o; C L <= VT, so at most one) up to kPre of its tiles, and the
+  // first of its costs for the weights (one thread per virtual thread only).
+  constexpr int kPre = R == 1 ? 16 : 1;
   const int rg = tid / L, o = u0 + (tid - rg * L);
   const int j0 = rg * n / C, j1 = tid < C * L ? (rg + 1) * n / C : j0;
   const bool item = tid < C * L && o < u1;
   double sv[kPre];
 #pragma unroll
-  for (int q = 0; q < kPre; ++q) sv[q] = (item && j0 + q < j1) ? d.partials[(size_t)(j0 + q) * kPartStride(T) + 4 + o] : 0.0;
+  for (int q = 0; q < kPre; ++q) sv[q] = (R == 1 && item && j0 + q < j1) ? d.partials[(size_t)(j0 + q) * kPartStride(T) + 4 + o] : 0.0;
   const int kb = (int)((long)K * c / ng), ke = (int)((long)K * (c + 1) / ng);
-  const float J0 = (d.wn && kb + tid < ke) ? d.J[kb + tid] : 0.0f;
-  // rho = min over tiles with weight (min is exact in any order)
-  double r = INFINITY;
-  for (int j = tid; j < n; j += kMergeThreads) {
-    const double* pj = d.partials + (size_t)j * kPartStride(T);
-    if (pj[1] > 0.0) r = fmin(r, pj[0]);
-  }
+  const float J0 = (R == 1 && (d.wn || d.J_copy) && kb + tid < ke) ? d.J[kb + tid] : 0.0f;
+  // rho = min over tiles with weight (min is exact in any order); with
+  // reuse, rho, the tile factors and the wave sums of an earlier group of
+  // the same solve are still in red and fac (the same values)
+  if (!reuse) {
+    double r = INFINITY;
+    for (int j = tid; j < n; j += NT) {
+      const double* pj = d.partials + (size_t)j * kPartStride(T);
+      if (pj[1] > 0.0) r = fmin(r, pj[0]);
+    }
 #pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) r = fmin(r, __shfl_xor(r, m, 64));
-  if (lane == 0) red[wave] = r;
+    for (int m = 32; m >= 1; m >>= 1) r = fmin(r, __shfl_xor(r, m, 64));
+    if (lane == 0) red[wave] = r;
+  }
   __syncthreads();
   double rho = red[0];
 #pragma unroll
-  for (int w = 1; w < NW; ++w) rho = fmin(rho, red[w]);
-  // tile factors, and eta, eta2 by a fixed tree
-  double e = 0.0, e2 = 0.0;
-  for (int j = tid; j < n; j += kMergeThreads) {
-    const double* pj = d.partials + (size_t)j * kPartStride(T);
-    const double f = (pj[1] > 0.0 && isfinite(rho)) ? exp(-(pj[0] - rho) * d.inv_lambda) : 0.0;
-    fac[j] = f;
-    e += pj[1] * f;
-    e2 += pj[2] * f * f;
-  }
-  e = wave_sum(e);
-  e2 = wave_sum(e2);
-  if (lane == 0) {
-    red[NW + wave] = e;
-    red[2 * NW + wave] = e2;
+  for (int w = 1; w < NT / 64; ++w) rho = fmin(rho, red[w]);
+  // tile factors, and eta, eta2 by a fixed tree over the VT threads
+#pragma unroll
+  for (int rr = 0; rr < (reuse ? 0 : R); ++rr) {
+    const int v = tid + rr * NT;
+    double e = 0.0, e2 = 0.0;
+    for (int j = v; j < n; j += VT) {
+      const double* pj = d.partials + (size_t)j * kPartStride(T);
+      const double f = (pj[1] > 0.0 && isfinite(rho)) ? exp(-(pj[0] - rho) * d.inv_lambda) : 0.0;
+      fac[j] = f;
+      e += pj[1] * f;
+      e2 += pj[2] * f * f;
+    }
+    e = wave_sum(e);
+    e2 = wave_sum(e2);
+    if (lane == 0) {
+      red[NW + (v >> 6)] = e;
+      red[2 * NW + (v >> 6)] = e2;
+    }
   }
   __syncthreads();
   double eta = 0.0, eta2 = 0.0;
@@ -1352,19 +1419,42 @@ __global__ __launch_bounds__(kMergeThreads) void k_fused_merge(FusedBatch batch)
   const bool ok = isfinite(rho) && eta > 0.0;
   double* res = d.result;
   // the slice of U*: partial sums over C tile ranges, each in tile order
-  if (ok && tid < C * L) {
-    double sacc = 0.0;
-    if (item) {
+  if (ok) {
+    if constexpr (R == 1) {
+      if (tid < C * L) {
+        double sacc = 0.0;
+        if (item) {
 #pragma unroll
-      for (int q = 0; q < kPre; ++q)
-        if (j0 + q < j1) sacc = fma(sv[q], fac[j0 + q], sacc);
+          for (int q = 0; q < kPre; ++q)
+            if (j0 + q < j1) sacc = fma(sv[q], fac[j0 + q], sacc);
 #pragma unroll 8
-      for (int j = j0 + kPre; j < j1; ++j) sacc = fma(d.partials[(size_t)j * kPartStride(T) + 4 + o], fac[j], sacc);
+          for (int j = j0 + kPre; j < j1; ++j) sacc = fma(d.partials[(size_t)j * kPartStride(T) + 4 + o], fac[j], sacc);
+        }
+        part[tid] = sacc;
+      }
+    } else {
+      for (int v = tid; v < C * L; v += NT) {
+        const int vg = v / L, vo = u0 + (v - vg * L);
+        const int a = vg * n / C, b = (vg + 1) * n / C;
+        double sacc = 0.0;
+        if (vo < u1) {
+          // eight reads in flight, the products in tile order
+          int j = a;
+          for (; j + 8 <= b; j += 8) {
+            double x[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) x[q] = d.partials[(size_t)(j + q) * kPartStride(T) + 4 + vo];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) sacc = fma(x[q], fac[j + q], sacc);
+          }
+          for (; j < b; ++j) sacc = fma(d.partials[(size_t)j * kPartStride(T) + 4 + vo], fac[j], sacc);
+        }
+        part[v] = sacc;
+      }
     }
-    part[tid] = sacc;
   }
   __syncthreads();
-  for (int i = u0 + tid; i < u1; i += kMergeThreads) {
+  for (int i = u0 + tid; i < u1; i += NT) {
     const int t = i >> 2, ch = i & 3;
     double U;
     if (ok) {
@@ -1382,10 +1472,11 @@ __global__ __launch_bounds__(kMergeThreads) void k_fused_merge(FusedBatch batch)
       if (t == T - 1) d.U_resident[t * 4 + ch] = U;
     }
   }
-  if (d.wn)
-    for (int k = kb + tid; k < ke; k += kMergeThreads) {
-      const float J = k == kb + tid ? J0 : d.J[k];
-      d.wn[k] = (ok && isfinite(J)) ? exp(-((double)J - rho) * d.inv_lambda) / eta : 0.0;
+  if (d.wn || d.J_copy)
+    for (int k = kb + tid; k < ke; k += NT) {
+      const float J = (R == 1 && k == kb + tid) ? J0 : d.J[k];
+      if (d.wn) d.wn[k] = (ok && isfinite(J)) ? exp(-((double)J - rho) * d.inv_lambda) / eta : 0.0;
+      if (d.J_copy) d.J_copy[k] = J;
     }
   if (c == 0 && tid == 0) {
     const uint32_t tick = d.tick_fixed == 0xFFFFFFFFu ? *d.tick_slot : d.tick_fixed;
@@ -1406,6 +1497,272 @@ __global__ __launch_bounds__(kMergeThreads) void k_fused_merge(FusedBatch batch)
       rr[RES_ETA] = 0.0;
     }
     if (d.tick_slot) *d.tick_slot = tick + 1u;
+  }
+}
+
+__global__ __launch_bounds__(kMergeThreads) void k_fused_merge(FusedBatch batch) {
+  extern __shared__ __align__(16) char lds[];
+  const SolveDesc& d = batch.descs[blockIdx.x];
+  if ((int)blockIdx.y >= merge_groups(d.T)) return;
+  double* red = (double*)lds;
+  merge_group<kMergeThreads>(d, blockIdx.y, red, red + 3 * (kMergeThreads / 64) + kMergeThreads);
+}
+
+// ------------------------------------------------------- served ring kernel
+//
+// Persistent kernel of the served path (see ring.hpp for the protocol): one
+// workgroup per compute unit claims ring items in publication order.  A
+// prep item copies a solve's upload block from pinned host memory into its
+// device block and folds the latent block of every gate; a tile item runs
+// one tile exactly as k_fused does; the workgroup that counts a solve's last
+// tile merges its partials exactly as k_fused_merge does (the same function,
+// the same summation order) and publishes the solve's completion.  Results,
+// weights and the cost copy go to pinned host memory named in the
+// descriptor, so the host reads them without a copy.
+
+// Extra LDS of the served kernel beyond the fused layout: the merge's
+// reductions and partial sums (its tile factors use the layout's fac table).
+constexpr size_t kServedMergeBytes = sizeof(double) * (3 * (kMergeThreads / 64) + kMergeThreads);
+
+// Host words are read with relaxed system-scope loads (coherent reads of
+// host memory); device words are polled with relaxed agent-scope loads.
+// Polling never fences: an acquire or release fence at agent or system scope
+// writes back or invalidates a whole L2 on this GPU, so fences stand only
+// where data changes hands (a tile's block, its partials, a solve's result).
+__device__ __forceinline__ uint64_t ring_host_load(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+__device__ __forceinline__ RingItem ring_host_item(const RingItem* p) {
+  const uint64_t* q = (const uint64_t*)p;
+  const uint64_t w0 = ring_host_load(q), w1 = ring_host_load(q + 1), w2 = ring_host_load(q + 2),
+                 w3 = ring_host_load(q + 3);
+  RingItem it;
+  it.block = w0;
+  it.src = w1;
+  it.slot = (uint32_t)w2;
+  it.k0 = (int32_t)(uint32_t)(w2 >> 32);
+  it.count = (uint32_t)w3;
+  it.seq = (uint32_t)(w3 >> 32);
+  return it;
+}
+
+// Device copies of the host's tails, refreshed by one thread
+// at a time (token) and at most once per refresh_ticks over the whole grid.
+__device__ __forceinline__ void ring_refresh(const RingArgs& r) {
+  const uint64_t now = __builtin_amdgcn_s_memrealtime();
+  if (now - __hip_atomic_load(r.poll_time, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < r.refresh_ticks) return;
+  uint32_t free_token = 0u;
+  if (!__hip_atomic_compare_exchange_strong(r.poll, &free_token, 1u, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT))
+    return;
+  const uint64_t pt = ring_host_load(r.ptail);
+  const uint64_t t = ring_host_load(r.tail);
+  __hip_atomic_fetch_max(r.dptail, pt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_fetch_max(r.dtail, t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(r.poll_time, now, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(r.poll, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Claim the next item of a queue (one thread) up to the device copy of its
+// tail: the head is advanced by compare-and-swap; the item is read (from
+// host memory, after the tail that covers it) before the claim: an item not
+// yet claimed is never rewritten by the host, so what was read is the item
+// the claim takes.
+__device__ __forceinline__ bool ring_claim(const RingItem* items, uint32_t cap, uint64_t* head,
+                                           const uint64_t* dtail, RingItem& it) {
+  uint64_t hd = __hip_atomic_load(head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const uint64_t t = __hip_atomic_load(dtail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  while (hd < t) {
+    it = ring_host_item(items + hd % cap);
+    if (__hip_atomic_compare_exchange_strong(head, &hd, hd + 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT))
+      return true;
+  }
+  return false;
+}
+
+__device__ __forceinline__ void ring_put(int* m, const RingItem& it) {
+  m[0] = (int)(uint32_t)it.block;
+  m[1] = (int)(uint32_t)(it.block >> 32);
+  m[2] = (int)(uint32_t)it.src;
+  m[3] = (int)(uint32_t)(it.src >> 32);
+  m[4] = (int)it.slot;
+  m[5] = it.k0;
+  m[6] = (int)it.count;
+  m[7] = (int)it.seq;
+}
+
+__device__ __forceinline__ RingItem ring_get(const int* m) {
+  RingItem it;
+  it.block = (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane(m[0]) |
+             ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane(m[1]) << 32);
+  it.src = (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane(m[2]) |
+           ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane(m[3]) << 32);
+  it.slot = (uint32_t)__builtin_amdgcn_readfirstlane(m[4]);
+  it.k0 = __builtin_amdgcn_readfirstlane(m[5]);
+  it.count = (uint32_t)__builtin_amdgcn_readfirstlane(m[6]);
+  it.seq = (uint32_t)__builtin_amdgcn_readfirstlane(m[7]);
+  return it;
+}
+
+// Output m of gate g of the latent fold, formed exactly as fold_gate forms
+// it (the same products in the same order), sixteen weight reads in flight.
+__device__ __forceinline__ void fold_one(const SolveDesc& d, int g, int m, const DeviceWeights& w) {
+  const int H = d.H;
+  float* cache = d.cf_cache ? d.cf_cache + (size_t)g * H : nullptr;
+  if ((d.fold_cached >> g) & 1u) {
+    d.cfold[g * H + m] = cache[m];
+    return;
+  }
+  const float* z = d.z + g * kLatent;
+  double acc = w.b0[m];
+#pragma unroll
+  for (int j0 = 0; j0 < kLatent; j0 += 16) {
+    double wv[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) wv[j] = w.w0lat[(size_t)(j0 + j) * H + m];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) acc = fma(wv[j], (double)z[j0 + j], acc);
+  }
+  d.cfold[g * H + m] = (float)acc;
+  if (cache) cache[m] = (float)acc;
+}
+
+// A prep item, on the whole workgroup: the host's mirror into the device
+// block, the folds (every gate at once over the workgroup), then the slot's
+// ready word.
+__device__ __forceinline__ void ring_prep(const RingArgs& ring, const RingItem& it, const DeviceWeights& w) {
+  const int tid = threadIdx.x;
+  const uint64_t* from = (const uint64_t*)it.src;
+  uint64_t* to = (uint64_t*)(ring.pool + it.block);
+  for (uint32_t i = tid; i < it.count / 8; i += kThreads) to[i] = ring_host_load(from + i);
+  __syncthreads();   // the workgroup reads its own stores back (one L1)
+  const SolveDesc& d = *(const SolveDesc*)(ring.pool + it.block);
+  if (d.sdf_kind == 0)
+    for (int i = tid; i < d.G * d.H; i += kThreads) fold_one(d, i / d.H, i % d.H, w);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");   // the block, for tiles anywhere on the device
+  __syncthreads();
+  if (tid == 0) __hip_atomic_store(ring.prep + it.slot, it.seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// The merge of a solve on one workgroup, group after group.
+__device__ __forceinline__ void ring_merge(const SolveDesc& d, double* scratch, double* fac) {
+  const int ng = merge_groups(d.T);
+  for (int c = 0; c < ng; ++c) {
+    merge_group<kThreads>(d, c, scratch, fac, c > 0);
+    __syncthreads();
+  }
+}
+
+template <int P, int H, int NHH, bool PE>
+__global__ __launch_bounds__(kThreads, 1) void k_served(RingArgs ring, DeviceWeights w, int Tm, int Gm,
+                                                         int max_tiles) {
+  constexpr int WPL = kWaves / NHH;
+  constexpr int MB = H / WPL / 16;
+  extern __shared__ __align__(16) char lds[];
+  const Views V = make_views<P, H, NHH>(lds, Tm, Gm, max_tiles, PE ? w.feat_k32 : 0);
+  double* mscratch = (double*)(lds + fused_lds<P, H, NHH>(Tm, Gm, max_tiles, PE ? w.feat_k32 : 0).total);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int h = lane >> 4, nl = lane & 15;
+  const int own = wave / WPL, gw = wave % WPL;
+  FragT<P> wreg[MB][H / 32];
+  const float scale_own = fused_setup<P, H, NHH, PE, MB>(V, w, tid, lane, own, gw, wreg);
+
+  uint64_t ticket = ~0ull;   // thread 0: the tile-queue index this workgroup holds
+  while (true) {
+    __syncthreads();
+    if (tid == 0) {
+      // a queued prep item first; else the item of this workgroup's ticket,
+      // once published (an exit item, or no item for wait_polls polls:
+      // leave)
+      int got = 0;
+      RingItem item{};
+      for (uint32_t n = 0;;) {
+        ring_refresh(ring);
+        if (ring_claim(ring.pitems, ring.pcap, ring.phead, ring.dptail, item)) {
+          got = 1;
+          break;
+        }
+        if (ticket == ~0ull) ticket = __hip_atomic_fetch_add(ring.head, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (ticket < __hip_atomic_load(ring.dtail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+          __atomic_signal_fence(__ATOMIC_SEQ_CST);
+          item = ring_host_item(ring.items + ticket % ring.cap);
+          ticket = ~0ull;
+          got = item.k0 != kRingExit;
+          break;
+        }
+        if (++n > ring.wait_polls) {
+          __hip_atomic_store(ring.lost, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(8);
+      }
+      V.misc[0] = got;
+      if (got) ring_put(V.misc + 1, item);
+    }
+    __syncthreads();
+    if (!__builtin_amdgcn_readfirstlane(V.misc[0])) break;
+    const RingItem it = ring_get(V.misc + 1);
+    if (it.k0 < 0) {
+      ring_prep(ring, it, w);
+      continue;
+    }
+    const uint32_t slot = it.slot, seq = it.seq, count = it.count;
+    const SolveDesc& d = *(const SolveDesc*)(ring.pool + it.block);
+
+    // tile: wait until the solve's block is ready, running queued prep items
+    // meanwhile (state 1 ready, 2 a prep item to run, 3 gave up, 0 wait)
+    int st = 0;
+    for (uint32_t n = 0;;) {
+      __syncthreads();
+      if (tid == 0) {
+        RingItem pi{};
+        int s0 = 0;
+        if (__hip_atomic_load(ring.prep + slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == seq) {
+          s0 = 1;
+        } else {
+          ring_refresh(ring);
+          if (ring_claim(ring.pitems, ring.pcap, ring.phead, ring.dptail, pi)) {
+            s0 = 2;
+            ring_put(V.misc + 1, pi);
+          } else if (++n > ring.wait_polls) {
+            s0 = 3;
+          } else {
+            __builtin_amdgcn_s_sleep(4);
+          }
+        }
+        V.misc[9] = s0;
+      }
+      __syncthreads();
+      st = __builtin_amdgcn_readfirstlane(V.misc[9]);
+      if (st == 1 || st == 3) break;
+      if (st == 2) ring_prep(ring, ring_get(V.misc + 1), w);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    const bool ok = st == 1;
+    if (ok) fused_tile<P, H, NHH, PE, MB>(V, d, w, it.k0, wave, lane, gw, h, nl, scale_own, wreg);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (tid == 0) {
+      if (!ok) __hip_atomic_store(ring.fail + slot, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      V.misc[10] = (int)__hip_atomic_fetch_add(ring.tiles + slot, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    if ((uint32_t)__builtin_amdgcn_readfirstlane(V.misc[10]) + 1u != count) continue;
+    // the solve's last tile: merge, then publish the completion
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    const bool failed = __hip_atomic_load(ring.fail + slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
+    if (!failed) ring_merge(d, mscratch, V.fac);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");   // the result in host memory, the warm start
+    __syncthreads();
+    if (tid == 0) {
+      __hip_atomic_store(ring.tiles + slot, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(ring.fail + slot, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(ring.done + slot, failed ? (seq | kRingFailBit) : seq, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_SYSTEM);
+    }
   }
 }
 
@@ -1907,6 +2264,59 @@ hipError_t launch_fused(const FusedBatch& b, int n_solves, const DeviceWeights& 
   const size_t merge_lds = sizeof(double) * (3 * (kMergeThreads / 64) + (size_t)max_tiles + kMergeThreads);
   hipLaunchKernelGGL(k_fused_merge, dim3(n_solves, merge_groups(max_T)), dim3(kMergeThreads), merge_lds, s, b);
   return hipGetLastError();
+}
+
+template <int P, int H, int NHH, bool PE>
+static hipError_t launch_served_t(const RingArgs& r, const DeviceWeights& w, int Tm, int Gm, int max_tiles,
+                                  int grid, hipStream_t s) {
+  const size_t bytes = fused_lds<P, H, NHH>(Tm, Gm, max_tiles, PE ? w.feat_k32 : 0).total + kServedMergeBytes;
+  {
+    static std::mutex mu;
+    static int max_set = 0;
+    std::lock_guard<std::mutex> lock(mu);
+    if ((int)bytes > max_set) {
+      hipError_t e = hipFuncSetAttribute((const void*)k_served<P, H, NHH, PE>,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+      if (e != hipSuccess) return e;
+      max_set = (int)bytes;
+    }
+  }
+  hipLaunchKernelGGL((k_served<P, H, NHH, PE>), dim3(grid), dim3(kThreads), bytes, s, r, w, Tm, Gm, max_tiles);
+  return hipGetLastError();
+}
+
+template <int P>
+static hipError_t launch_served_p(const RingArgs& r, const DeviceWeights& w, int Tm, int Gm, int mt, int grid,
+                                  hipStream_t s) {
+  const int nhh = w.n_hidden - 1;
+  const bool pe = w.feat_ksteps > 0;
+  if (w.H == 128 && nhh == 1) return pe ? launch_served_t<P, 128, 1, true>(r, w, Tm, Gm, mt, grid, s) : launch_served_t<P, 128, 1, false>(r, w, Tm, Gm, mt, grid, s);
+  if (w.H == 128 && nhh == 2) return pe ? launch_served_t<P, 128, 2, true>(r, w, Tm, Gm, mt, grid, s) : launch_served_t<P, 128, 2, false>(r, w, Tm, Gm, mt, grid, s);
+  if (w.H == 256 && nhh == 1) return pe ? launch_served_t<P, 256, 1, true>(r, w, Tm, Gm, mt, grid, s) : launch_served_t<P, 256, 1, false>(r, w, Tm, Gm, mt, grid, s);
+  if (w.H == 256 && nhh == 2) return pe ? launch_served_t<P, 256, 2, true>(r, w, Tm, Gm, mt, grid, s) : launch_served_t<P, 256, 2, false>(r, w, Tm, Gm, mt, grid, s);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_served(const RingArgs& r, const DeviceWeights& w, int max_T, int max_G, int max_tiles,
+                         hipStream_t s) {
+  int dev = 0, ncu = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  const int grid = std::max(1, ncu);
+  switch (w.precision) {
+    case P_BF16: return launch_served_p<P_BF16>(r, w, max_T, max_G, max_tiles, grid, s);
+    case P_BF16X2: return launch_served_p<P_BF16X2>(r, w, max_T, max_G, max_tiles, grid, s);
+    case P_BF16X3: return launch_served_p<P_BF16X3>(r, w, max_T, max_G, max_tiles, grid, s);
+    case P_FP8: return launch_served_p<P_FP8>(r, w, max_T, max_G, max_tiles, grid, s);
+    case P_F16X2: return launch_served_p<P_F16X2>(r, w, max_T, max_G, max_tiles, grid, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+size_t served_lds_bytes(int precision, int H, int n_hidden, int Tm, int Gm, int max_tiles, int feat_ks) {
+  if (H != 128 && H != 256) return 0;
+  return fused_lds_bytes(precision, H, n_hidden, Tm, Gm, max_tiles, feat_ks) + kServedMergeBytes;
 }
 
 hipError_t tune_wide_region(const FusedBatch& b, int n_solves, const DeviceWeights& w, int max_T, int max_G,

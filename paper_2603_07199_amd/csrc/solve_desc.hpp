@@ -74,6 +74,7 @@ struct SolveDesc {
   double* partials;      // per tile: rho, eta, S[T][4]
   int32_t tile_rollouts; // rollouts per fused tile
   int32_t n_tiles;
+  float* J_copy;         // [K] copy of J written with the normalised weights, or NULL
 };
 
 }  // namespace mppi

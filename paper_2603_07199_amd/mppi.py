@@ -27,6 +27,7 @@ PREC = {"fp32": 0, "bf16": 1, "bf16x2": 2, "fp8": 3, "bf16x3": 4, "f16x2": 5}
 PATH = {"plain": 0, "fused": 1}
 SDF = {"mlp": 0, "analytic": 1}
 CFG_TIMING = 1
+CFG_SERVE_BATCHES = 2   # served path in batched launches instead of the work ring
 REQ_NO_SHIFT = 1
 REQ_SDF_AT_P0 = 2
 TICK_RESIDENT = 0xFFFFFFFF
@@ -89,7 +90,7 @@ class mppi_stats(C.Structure):
         ("failed", C.c_uint64), ("waves", C.c_uint64), ("bytes_in_use", C.c_uint64),
         ("bytes_peak", C.c_uint64), ("budget", C.c_uint64), ("sdf_launches", C.c_uint64),
         ("sdf_ms", C.c_double), ("solve_launches", C.c_uint64), ("solve_ms", C.c_double),
-        ("tune_runs", C.c_uint64), ("wide_region", C.c_uint64),
+        ("tune_runs", C.c_uint64), ("wide_region", C.c_uint64), ("ring_launches", C.c_uint64),
     ]
 
 
@@ -358,13 +359,15 @@ def default_config(model, K_max=8192, T_max=64, G_max=8, hidden=256, n_hidden=3,
                    precision="fp32", path="plain", sdf_kind="mlp", max_instances=4096,
                    max_inflight=64, queue_depth=4096, budget=1 << 30, seed=0, timing=False,
                    stream=None, device_pool=None, device_pool_bytes=0, pe_freqs=0, wave_queries_max=0,
-                   wide_region=0):
+                   wide_region=0, serve="ring"):
+    if serve not in ("ring", "batches"):
+        raise ValueError(f"serve must be 'ring' or 'batches', not {serve!r}")
     return {
         "precision": PREC[precision], "path": PATH[path], "sdf_kind": SDF[sdf_kind],
         "hidden": hidden, "n_hidden": n_hidden, "latent_dim": 64,
         "K_max": K_max, "T_max": T_max, "G_max": G_max,
         "max_instances": max_instances, "max_inflight": max_inflight, "queue_depth": queue_depth,
-        "device": 0, "flags": CFG_TIMING if timing else 0,
+        "device": 0, "flags": (CFG_TIMING if timing else 0) | (CFG_SERVE_BATCHES if serve == "batches" else 0),
         "hbm_budget_bytes": int(budget), "seed": int(seed),
         "mass": float(model["mass"]), "gravity": float(model["gravity"]),
         "u_lo": list(model["u_lo"]), "u_hi": list(model["u_hi"]),

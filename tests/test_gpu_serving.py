@@ -1,5 +1,7 @@
 """Served path (mppi_submit / mppi_poll): continuous batching of uneven
-solves into fused launches.
+solves on the fused decoder, through the work ring of the persistent served
+kernel (the default; tests/test_gpu_ring.py compares it with batched
+launches).
 
 * Alone vs in the mix: a request's result does not depend on what it was
   batched with (fixed tile partition per solve, merge in tile order), so the
