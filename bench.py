@@ -96,7 +96,7 @@ def _softplus_per_query(layers):
     return sum(layers[1:-1])
 
 
-KERNEL_HEADERS = ("device_common.hpp", "kernels.hpp", "solve_desc.hpp", "weights.hpp")
+KERNEL_HEADERS = ("device_common.hpp", "kernels.hpp", "ring.hpp", "solve_desc.hpp", "weights.hpp")
 
 
 def _source_hash(path):
@@ -212,11 +212,14 @@ def served_leg(M, precision, n_req, plain_subset=64):
     """Uneven requests (K in {1024..8192}, T in {20..60}, G = 1, own instance
     each) arriving as a Poisson stream (mean gap 50 us), every 16th replaced by
     a probe of the benchmark shape (K=4096, T=50, G=4); served through
-    mppi_submit / mppi_poll.  The stream runs twice: at the specified rate,
-    and with the gaps stretched so that the offered work is 80% of the rate
-    the first run served (latency under a load the GPU keeps up with).  The
-    plain FP32 path runs the first plain_subset requests one solve per
-    launch, back to back, for comparison."""
+    mppi_submit / mppi_poll through the work ring of the persistent served
+    kernel.  The stream runs twice: at the specified rate, and with the gaps
+    stretched so that the offered work is 80% of the rate the first run
+    served (latency under a load the GPU keeps up with); then the highest
+    load that keeps the probes' p99 under 5 ms is searched.  The same two
+    streams also run through the batched served launches, and the plain
+    FP32 path runs the first plain_subset requests one solve per launch,
+    back to back, for comparison."""
     reqs = sc.serving_requests(n_req=n_req)
     probe = sc.config_problem("P2", 99)
     items = []
@@ -267,6 +270,24 @@ def served_leg(M, precision, n_req, plain_subset=64):
             break
     out["max_load_probe_p99_under_5ms"] = best
     eng.close()
+    # the same two streams through the batched served launches (one launch
+    # per admission pass) instead of the work ring
+    out["mode"] = "ring"
+    engb = M.Engine((W, b), sc.MODEL, K_max=8192, T_max=60, G_max=4, hidden=256, n_hidden=3,
+                    precision=precision, path="fused", budget=8 << 30, queue_depth=4096,
+                    max_inflight=4096, max_instances=24 * n_req + 16, serve="batches")
+    rc, t = engb.submit(warm)
+    while engb.poll(t, warm["K"], warm["T"])[0] == M.MPPI_PENDING:
+        time.sleep(1e-4)
+    bat = {}
+    for key, g, off in (("at_specified_rate", 1.0, 0), ("at_the_ring_80pct_stream", scale, 2 * n_req)):
+        if key == "at_the_ring_80pct_stream" and scale <= 1.0:
+            continue
+        r = _serve(M, engb, items, g, off)
+        r.pop("probe_ms"), r.pop("all_ms")
+        bat[key] = r
+    out["batched_launches"] = bat
+    engb.close()
     # the same kind of requests through the plain FP32 one-solve-per-launch path
     sub = [p for _, p, _ in items[:plain_subset]]
     pe = M.Engine((W, b), sc.MODEL, K_max=8192, T_max=60, G_max=4, hidden=256, n_hidden=3,

@@ -76,10 +76,7 @@ __device__ __forceinline__ void sample_control(const SolveDesc& d, uint32_t k, u
 // (Section III-B), shared by all queries of a gate.  With an instance cache
 // (object permanence, Section IV-B-3) an observed gate's fold is also stored
 // there, and an unobserved gate's fold is taken from it.  One workgroup per
-// gate (any size).  AHEAD weight reads are in flight before their products
-// (all 64 by default, one memory latency; fewer where registers are short);
-// the products run in the same order either way.
-template <int AHEAD = kLatent>
+// gate (any size).
 __device__ __forceinline__ void fold_gate(const SolveDesc& d, int g, const DeviceWeights& w) {
   if (g >= d.G || d.sdf_kind != 0) return;
   float* cache = d.cf_cache ? d.cf_cache + (size_t)g * d.H : nullptr;
@@ -89,17 +86,14 @@ __device__ __forceinline__ void fold_gate(const SolveDesc& d, int g, const Devic
   }
   const float* z = d.z + g * kLatent;
   for (int m = threadIdx.x; m < d.H; m += blockDim.x) {
-    // (the transposed block: neighbouring threads read neighbouring words)
-    static_assert(kLatent % AHEAD == 0, "whole read groups");
+    // (the transposed block: neighbouring threads read neighbouring words;
+    // all 64 reads go out before the first product, one memory latency)
+    double wv[kLatent];
+#pragma unroll
+    for (int j = 0; j < kLatent; ++j) wv[j] = w.w0lat[(size_t)j * d.H + m];
     double acc = w.b0[m];
 #pragma unroll
-    for (int j0 = 0; j0 < kLatent; j0 += AHEAD) {
-      double wv[AHEAD];
-#pragma unroll
-      for (int j = 0; j < AHEAD; ++j) wv[j] = w.w0lat[(size_t)(j0 + j) * d.H + m];
-#pragma unroll
-      for (int j = 0; j < AHEAD; ++j) acc = fma(wv[j], (double)z[j0 + j], acc);
-    }
+    for (int j = 0; j < kLatent; ++j) acc = fma(wv[j], (double)z[j], acc);
     d.cfold[g * d.H + m] = (float)acc;
     if (cache) cache[m] = (float)acc;
   }
