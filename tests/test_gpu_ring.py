@@ -147,3 +147,37 @@ def test_ring_close_with_work_in_flight():
     probs = _mixed(8, seed=13)
     _submit_all(eng, probs)
     eng.close()      # destroy waits for the published solves, then stops the kernel
+
+
+@pytest.mark.parametrize("variant", ["pe2-f16x2-h256x2", "pe1-bf16-h128x1", "rotor-bf16x3-h256x2", "rotor-bf16-h128x2"])
+def test_ring_positional_encoding_and_rotor_rates(variant):
+    """The ring kernel's other instantiations (encoded-point layer 1, the
+    rotor-thrust-rate input) against the blocking solve, bit for bit."""
+    M = require_gpu()
+    kind, precision, shape = variant.split("-")
+    H, L = int(shape[1:4]), int(shape[-1])
+    if kind.startswith("pe"):
+        F = int(kind[2:])
+        W, b = sc.xavier_weights((3 + 6 * F + 64,) + (H,) * (L + 1) + (1,), seed=10 + F, bias_scale=0.2)
+        model, kw = sc.MODEL, dict(pe_freqs=F)
+        probs = [sc.make_problem(K, T, G, seed=60 + i, instance_id=500 + i, d_safe=1.0)
+                 for i, (K, T, G) in enumerate(((256, 20, 4), (100, 13, 2), (16, 1, 1)))]
+    else:
+        W, b = sc.xavier_weights((67,) + (H,) * (L + 1) + (1,), seed=8, bias_scale=0.2)
+        model, kw = sc.ROTOR_MODEL, {}
+        probs = [sc.rotor_problem(K, T, G, seed=1 + i, rot="haar", start="moving", d_safe=1.0, Q_vis=0.3,
+                                  instance_id=600 + i)
+                 for i, (K, T, G) in enumerate(((256, 20, 4), (100, 13, 2), (16, 1, 1)))]
+    cfg = dict(K_max=256, T_max=20, G_max=4, hidden=H, n_hidden=L + 1, precision=precision, path="fused",
+               budget=256 << 20, **kw)
+    ring = M.Engine((W, b), model, **cfg)
+    alone = M.Engine((W, b), model, **cfg)
+    res = _wait(ring, _submit_all(ring, probs), probs)
+    assert ring.stats()["ring_launches"] >= 1
+    for p, (rc, r) in zip(probs, res):
+        a = alone.step(p)
+        assert rc == 0 and a["rc"] == 0
+        assert np.array_equal(r["U_star"], a["U_star"]) and np.array_equal(r["J"], a["J"]), (variant, p["K"])
+    say(f"ring {variant}: {len(probs)} solves equal to the blocking solve")
+    ring.close()
+    alone.close()
