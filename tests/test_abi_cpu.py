@@ -234,3 +234,14 @@ def test_request_marshals_unobserved_gates_as_null_latent():
     assert z0[5] == np.float32(prob["gate_z"][0][5])
     r_all = _Request(prob).req
     assert all(bool(r_all.gates[g].z) for g in range(3))
+
+
+def test_config_flags_match_header():
+    """The binding's config flag values are the header's (MPPI_CFG_*)."""
+    hdr = open(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "mppi.h")).read()
+    flags = {m.group(1): 1 << int(m.group(2)) for m in re.finditer(r"#define MPPI_CFG_(\w+) \(1u << (\d+)\)", hdr)}
+    assert flags == {"TIMING": M.CFG_TIMING, "SERVE_BATCHES": M.CFG_SERVE_BATCHES}
+    cfg = M.default_config({"mass": 1.0, "gravity": 9.81, "u_lo": [0] * 4, "u_hi": [1] * 4}, serve="batches")
+    assert cfg["flags"] == M.CFG_SERVE_BATCHES
+    with pytest.raises(ValueError):
+        M.default_config({"mass": 1.0, "gravity": 9.81, "u_lo": [0] * 4, "u_hi": [1] * 4}, serve="waves")
