@@ -1438,16 +1438,15 @@ __device__ void merge_group(const SolveDesc& d, int c, double* lds, double* fac,
         const int a = vg * n / C, b = (vg + 1) * n / C;
         double sacc = 0.0;
         if (vo < u1) {
-          // eight reads in flight, the products in tile order
-          int j = a;
-          for (; j + 8 <= b; j += 8) {
+          // up to eight reads in flight, the products in tile order
+          for (int j = a; j < b; j += 8) {
             double x[8];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) x[q] = d.partials[(size_t)(j + q) * kPartStride(T) + 4 + vo];
+            for (int q = 0; q < 8; ++q) x[q] = j + q < b ? d.partials[(size_t)(j + q) * kPartStride(T) + 4 + vo] : 0.0;
 #pragma unroll
-            for (int q = 0; q < 8; ++q) sacc = fma(x[q], fac[j + q], sacc);
+            for (int q = 0; q < 8; ++q)
+              if (j + q < b) sacc = fma(x[q], fac[j + q], sacc);
           }
-          for (; j < b; ++j) sacc = fma(d.partials[(size_t)j * kPartStride(T) + 4 + vo], fac[j], sacc);
         }
         part[v] = sacc;
       }
