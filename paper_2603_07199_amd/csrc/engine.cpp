@@ -1227,6 +1227,7 @@ int mppi_batch_create(mppi_engine* e, const mppi_request* reqs, int32_t n, mppi_
   if (e->sticky.load()) return MPPI_EDEVICE;
   std::lock_guard<std::mutex> lk(e->mu);
   hipSetDevice(e->dev);
+  if (ring_end_launch(e) != MPPI_OK) return MPPI_EDEVICE;   // the uploads may run as copy kernels
   auto b = std::make_unique<mppi_batch>();
   std::vector<const mppi_request*> rs;
   uint64_t fp = 0;
@@ -1305,6 +1306,8 @@ int mppi_batch_wait(mppi_engine* e, mppi_batch* b) {
 int mppi_batch_results(mppi_engine* e, mppi_batch* b, mppi_result* results) {
   if (!e || !b || !results) return MPPI_EINVAL;
   std::lock_guard<std::mutex> lk(e->mu);
+  hipSetDevice(e->dev);
+  if (ring_end_launch(e) != MPPI_OK) return MPPI_EDEVICE;   // the read-backs may run as copy kernels
   hipStream_t st = e->streams[0];
   for (auto& s : b->st.solves) {
     int rc = enqueue_fetch(e, s.get(), st);
@@ -1635,7 +1638,8 @@ void ring_publish_exits(mppi_engine* e) {
 }
 
 // Called with the engine lock held by a path that launches kernels of its
-// own (blocking solve, staged batch): the ring kernel holds every compute
+// own (blocking solve, staged batch; the HIP runtime's copies of uploads and
+// read-backs may run as kernels too): the ring kernel holds every compute
 // unit while it runs, so its launch ends first.  Its exit items go behind
 // everything already published, which the kernel finishes without the host;
 // the scheduler retires those solves as usual.

@@ -181,3 +181,28 @@ def test_ring_positional_encoding_and_rotor_rates(variant):
     say(f"ring {variant}: {len(probs)} solves equal to the blocking solve")
     ring.close()
     alone.close()
+
+
+def test_staged_batch_while_ring_kernel_resident():
+    """A staged batch created, run and read back while served requests keep
+    the ring kernel resident (its uploads and read-backs may need compute
+    units): everything completes and equals the blocking solve."""
+    M = require_gpu()
+    eng, _ = _engine(M)
+    alone, _ = _engine(M)
+    served = _mixed(10, seed=17)
+    tickets = _submit_all(eng, served[:5])
+    staged = [dict(p, instance_id=7000 + i) for i, p in enumerate(_mixed(3, seed=19))]
+    bt = eng.batch(staged)
+    tickets += _submit_all(eng, served[5:])
+    bt.run()
+    bt.wait()
+    res_b = bt.results()
+    res_s = _wait(eng, tickets, served)
+    for p, r in zip(staged, res_b):
+        assert r["status"] == 0 and np.array_equal(r["U_star"], alone.step(p)["U_star"])
+    for p, (rc, r) in zip(served, res_s):
+        assert rc == 0 and np.array_equal(r["U_star"], alone.step(p)["U_star"])
+    bt.close()
+    eng.close()
+    alone.close()
