@@ -302,9 +302,9 @@ uint64_t mppi_solve_footprint(const mppi_engine* engine, int32_t K, int32_t T, i
  * EAGAIN while served solves hold too much of it.
  * Launches are asynchronous on the engine's stream; mppi_batch_wait blocks
  * until they finish; mppi_batch_results copies the latest outcome of request
- * i into results[i] (caller-owned, U_star sized T_i x 4).  mppi_batch_create,
- * mppi_batch_run and mppi_batch_results (like mppi_step and
- * mppi_step_noalloc) first end a resident served-ring launch: the work
+ * i into results[i] (caller-owned, U_star sized T_i x 4).  Every mppi_batch_*
+ * call that waits on or launches device work (like mppi_step and
+ * mppi_step_noalloc) first ends a resident served-ring launch: the work
  * already published finishes, then the call proceeds, and the ring
  * relaunches for the next served request. */
 typedef struct mppi_batch mppi_batch;

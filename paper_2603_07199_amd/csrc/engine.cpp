@@ -1293,6 +1293,10 @@ int mppi_batch_run(mppi_engine* e, mppi_batch* b) {
 int mppi_batch_wait(mppi_engine* e, mppi_batch* b) {
   if (!e || !b) return MPPI_EINVAL;
   std::lock_guard<std::mutex> lk(e->mu);
+  hipSetDevice(e->dev);
+  // a ring launch started since the batch ran would hold compute units the
+  // batch may still need while this call holds the lock its exits need
+  if (ring_end_launch(e) != MPPI_OK) return MPPI_EDEVICE;
   const hipError_t err = hipStreamSynchronize(e->streams[0]);
   if (err != hipSuccess) return dev_fail(e, err);
   if (b->launched) {
@@ -1328,6 +1332,8 @@ int mppi_batch_results(mppi_engine* e, mppi_batch* b, mppi_result* results) {
 int mppi_batch_destroy(mppi_engine* e, mppi_batch* b) {
   if (!e || !b) return MPPI_EINVAL;
   std::lock_guard<std::mutex> lk(e->mu);
+  hipSetDevice(e->dev);
+  ring_end_launch(e);   // as in mppi_batch_wait; the batch is released either way
   hipStreamSynchronize(e->streams[0]);
   release_staged(e, b->st, true);
   e->adm->unreserve(b->reserved);
