@@ -206,3 +206,26 @@ def test_staged_batch_while_ring_kernel_resident():
     bt.close()
     eng.close()
     alone.close()
+
+
+def test_ring_at_the_largest_accepted_solve():
+    """The ring at the engine's largest shapes (K = 16384: 1024 tiles per
+    solve and 1024 tile factors in the merge; T = 128: 16 merge groups and
+    four-step scan chunks; G = 8), beside a ragged solve, against the
+    blocking solve bit for bit."""
+    M = require_gpu()
+    kw = dict(K_max=16384, T_max=128, G_max=8, precision="bf16", budget=2 << 30)
+    eng, _ = _engine(M, **kw)
+    alone, _ = _engine(M, **kw)
+    probs = [sc.make_problem(16384, 128, 8, seed=81, instance_id=1, d_safe=1.0),
+             sc.make_problem(5000, 97, 3, seed=82, instance_id=2, d_safe=1.0)]
+    res = _wait(eng, _submit_all(eng, probs), probs)
+    assert eng.stats()["ring_launches"] >= 1
+    for p, (rc, r) in zip(probs, res):
+        a = alone.step(p)
+        assert rc == 0 and a["rc"] == 0
+        for key in ("U_star", "J", "w"):
+            assert np.array_equal(r[key], a[key]), (key, p["K"], p["T"], p["G"])
+    say("ring at K=16384 T=128 G=8 and K=5000 T=97 G=3: equal to the blocking solve")
+    eng.close()
+    alone.close()
