@@ -54,8 +54,9 @@ hipError_t tune_wide_region(const FusedBatch& b, int n_solves, const DeviceWeigh
                             int max_tiles, hipStream_t s, int* best);
 
 // Served path: the persistent ring kernel (see ring.hpp), one workgroup per
-// compute unit, for H <= 256; it runs until the ring's stop word is set or
-// its workgroups find no item for the ring's idle_polls polls.  max_T,
+// compute unit, for H <= 256; it runs until each workgroup has taken one of
+// the exit items the host publishes (or, without the host, until a bounded
+// wait gives up).  max_T,
 // max_G, max_tiles: the largest solve the engine accepts (LDS layout).
 hipError_t launch_served(const RingArgs& r, const DeviceWeights& w, int max_T, int max_G, int max_tiles,
                          hipStream_t s);
